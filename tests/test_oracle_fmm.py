@@ -1,0 +1,203 @@
+"""Pins of the oracle's tree, direct sum and whole FMM (brute force, invariants, the definition)."""
+import numpy as np
+import pytest
+
+from oracle import direct, tree as otree
+from oracle.ffmm import Plan
+from oracle.quadrature import level_quadrature
+from oracle.resample import resample_sig
+
+
+def _cube(n, seed=0):
+    return np.random.default_rng(seed).random((n, 3))
+
+
+def _sphere(n, seed=0):
+    g = np.random.default_rng(seed).standard_normal((n, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def _charges(n, seed=1):
+    r = np.random.default_rng(seed)
+    return r.standard_normal(n) + 1j * r.standard_normal(n)
+
+
+# --- direct sum (the definition) ----------------------------------------------------------
+
+def test_direct_two_points_closed_form():
+    x = np.array([[0.0, 0.0, 0.0], [0.3, -0.4, 1.2]])
+    q = np.array([1.0 + 2.0j, -0.5 + 0.25j])
+    k = 5.0
+    d = 1.3
+    g = np.exp(1j * k * d) / d
+    assert np.allclose(direct.matvec(x, q, k), [g * q[1], g * q[0]], rtol=1e-15)
+
+
+def test_direct_brute_force_and_symmetry():
+    x = _cube(60)
+    x[7] = x[3]                      # a coincident pair is skipped
+    q = _charges(60)
+    k = 11.0
+    r = np.linalg.norm(x[:, None] - x[None], axis=-1)
+    a = np.where(r > 0, np.exp(1j * k * r) / np.where(r > 0, r, 1), 0)
+    assert np.allclose(direct.matvec(x, q, k), a @ q, rtol=1e-13)
+    assert np.allclose(a, a.T)
+    sub = np.array([5, 7, 59])
+    assert np.allclose(direct.matvec(x, q, k, targets=sub), (a @ q)[sub], rtol=1e-13)
+
+
+def test_direct_gradient_finite_difference():
+    x = _cube(40, seed=4)
+    q = _charges(40, seed=5)
+    k = 7.0
+    f = direct.gradient(x, q, k)
+    h = 1e-6
+    for i in (0, 17):
+        for a in range(3):
+            xp = x.copy(); xp[i, a] += h
+            xm = x.copy(); xm[i, a] -= h
+            fd = (direct.matvec(xp, q, k, targets=[i]) - direct.matvec(xm, q, k, targets=[i])) / (2 * h)
+            assert abs(fd[0] - f[i, a]) < 1e-6 * abs(f[i, a]) + 1e-7
+
+
+# --- octree -------------------------------------------------------------------------------
+
+def test_morton_small_example():
+    idx = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [3, 2, 1], [5, 6, 7]])
+    keys = otree.morton(idx, 3)
+    assert list(keys[:3]) == [1, 2, 4]
+    # x=011, y=010, z=001 -> bits (b0: x1 y0 z1)(b1: x1 y1 z0)(b2: 0 0 0)
+    assert keys[3] == 0b000_011_101
+    assert np.array_equal(otree.demorton(keys, 3), idx)
+
+
+def test_quantize_and_stable_sort():
+    x = np.array([[0.0, 0, 0], [1.0, 1, 1], [0.5, 0.5, 0.5], [0.0, 0, 0], [0.99999, 0.2, 0.7]])
+    t = otree.Tree(x, depth=2)
+    assert np.array_equal(t.idx[1], [3, 3, 3])           # the max corner is clamped
+    assert np.array_equal(t.idx[2], [2, 2, 2])
+    assert t.perm[0] == 0 and t.perm[1] == 3              # ties keep the input order
+
+
+def test_interaction_list_counts_dense_grid():
+    """Section 3.2: 316 distinct transfer vectors per level; a box has at most 189 interaction
+    boxes and at most 27 neighbours (itself included)."""
+    g = (np.stack(np.meshgrid(*[np.arange(16)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) / 16
+    t = otree.Tree(g, depth=4)
+    offs = set()
+    for l in (3, 4):
+        (ptr, _), codes = t.ilist[l], t.ioff[l]
+        assert np.diff(ptr).max() == 189
+        offs |= set(codes.tolist())
+        nptr, _ = t.neighbors[l]
+        assert np.diff(nptr).max() == 27
+    assert len(offs) == 316
+    semi = [d for d in (np.array([c % 7 - 3, (c // 7) % 7 - 3, c // 49 - 3]) for c in offs)
+            if d[0] >= 0 and d[1] >= 0 and d[2] >= 0 and d[0] >= d[1]]
+    assert len(semi) == 34
+
+
+def test_interaction_list_definition_brute_force():
+    x = _sphere(700, seed=2)
+    t = otree.Tree(x, depth=4)
+    for l in (2, 3, 4):
+        lev, par = t.levels[l], t.levels[l - 1]
+        (ptr, src), codes = t.ilist[l], t.ioff[l]
+        for b in range(lev.n):
+            want = []
+            for c in range(lev.n):
+                near = np.max(np.abs(lev.ijk[c] - lev.ijk[b])) <= 1
+                pnear = np.max(np.abs(par.ijk[t.parent[l][c]] - par.ijk[t.parent[l][b]])) <= 1
+                if pnear and not near:
+                    want.append(c)
+            assert list(src[ptr[b]:ptr[b + 1]]) == want
+            d = lev.ijk[src[ptr[b]:ptr[b + 1]]] - lev.ijk[b]
+            assert np.array_equal(codes[ptr[b]:ptr[b + 1]], otree.offset_code(d))
+
+
+def test_every_pair_counted_once():
+    """The near field (leaf neighbours) and the interaction lists of all levels together cover
+    every ordered pair of distinct boxes exactly once (Section 2)."""
+    x = _cube(600, seed=9)
+    t = otree.Tree(x, depth=4)
+    L = t.depth
+    leaf = t.levels[L]
+    cover = np.zeros((leaf.n, leaf.n), dtype=int)
+    nptr, nb = t.neighbors[L]
+    for b in range(leaf.n):
+        cover[b, nb[nptr[b]:nptr[b + 1]]] += 1
+    anc = {L: np.arange(leaf.n)}
+    for l in range(L, 2, -1):
+        anc[l - 1] = t.parent[l][anc[l]]
+    for l in range(2, L + 1):
+        (ptr, src), _ = t.ilist[l], t.ioff[l]
+        for b in range(leaf.n):
+            B = anc[l][b]
+            s = set(src[ptr[B]:ptr[B + 1]].tolist())
+            cover[b] += np.isin(anc[l], list(s)).astype(int)
+    assert np.all(cover == 1)
+
+
+# --- five-step resample ---------------------------------------------------------------------
+
+def test_five_step_resample_plane_wave():
+    """Section 3.4: a plane wave e^{i ka s.d} with small |d| is band-limited well below both
+    grids, so the five steps reproduce its samples on the other quadrature."""
+    q1, _ = level_quadrature(6.0, 1 / np.sqrt(3), 1e-10)
+    q2, _ = level_quadrature(12.0, 1 / np.sqrt(3), 1e-10)
+    d = np.array([0.3, -0.2, 0.25])
+    f1 = np.exp(1j * 6.0 * q1.dirs() @ d)
+    f2 = np.exp(1j * 6.0 * q2.dirs() @ d)
+    assert np.allclose(resample_sig(f1, q1, q2), f2, atol=1e-10)
+    assert np.allclose(resample_sig(f2, q2, q1), f1, atol=1e-10)
+
+
+def test_five_step_resample_uniform_rows_roundtrip():
+    """With every row of equal length the five steps are tensor-product Fourier resamples, so
+    interpolating up and anterpolating back is the identity (Section 3.1.3)."""
+    from oracle.quadrature import LevelQuad
+    q1 = LevelQuad(5, 12, [12] * 7)
+    q2 = LevelQuad(9, 20, [20] * 11)
+    # data with the spherical symmetry and a band inside the coarse grid
+    d = np.array([0.2, 0.1, -0.3])
+    g = np.exp(1j * 2.0 * q1.dirs() @ d) + 0.5 * q1.dirs()[:, 2] ** 2
+    back = resample_sig(resample_sig(g, q1, q2), q2, q1)
+    assert np.allclose(back, resample_sig(g, q1, q1), atol=1e-13)
+
+
+# --- whole matvec -----------------------------------------------------------------------------
+
+def test_fmm_cube_fp64_meets_eps():
+    """Volumetric workload (N = 4096 in the unit cube, kappa = 8 pi, depth 3, eps 1e-6)
+    against the full direct sum."""
+    x = _cube(4096)
+    q = _charges(4096)
+    k = 8 * np.pi
+    p = Plan(x, k, 1e-6, depth=3)
+    out = p.matvec(q)
+    ref = direct.matvec(x, q, k)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-6
+
+
+def test_fmm_error_falls_with_eps():
+    x = _sphere(3000)
+    q = _charges(3000)
+    k = 30.0
+    ref = direct.matvec(x, q, k)
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        out = Plan(x, k, eps, depth=4).matvec(q)
+        errs.append(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 1e-4 and errs[2] < 1e-6
+
+
+def test_fmm_multilevel_matches_single_level():
+    """Adding levels (more M2M/L2L passes) leaves the result within eps of the direct sum."""
+    x = _cube(1500, seed=3)
+    q = _charges(1500, seed=4)
+    k = 12.0
+    ref = direct.matvec(x, q, k)
+    for depth in (2, 3, 4):
+        out = Plan(x, k, 1e-5, depth=depth).matvec(q)
+        assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-5, depth

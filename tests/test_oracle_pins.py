@@ -1,0 +1,239 @@
+"""Pins of the oracle's building blocks to values the paper prints and to closed forms."""
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import fourier, special as osp, transfer, quadrature
+from oracle.quadrature import LevelQuad
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    return np.loadtxt(os.path.join(GOLDEN, name), comments="#")
+
+
+# --- Fig. SINconv / SINFspec (Section 3.1.2): printed numbers --------------------------------
+
+def test_sinconv_printed_values():
+    """All 47 printed points of Fig. SINconv: filtered quadrature with K = 2N + 2 samples and the
+    |sin| spectrum truncated to |n| <= N, the trapezoid rule with the same K, and 90/K^2."""
+    data = _load("sinconv.txt")
+    exact = np.sin(64.0) / 16.0
+    g = lambda t: np.cos(64.0 * np.cos(t))
+    for n, v_filt, v_trap, v_guide in data:
+        n = int(n)
+        k = 2 * n + 2
+        e_f = abs(fourier.sin_filtered_quadrature(g, n, k) - exact) / abs(exact)
+        e_t = abs(fourier.trapezoid_quadrature(g, k) - exact) / abs(exact)
+        if v_filt > 1e-12:
+            assert abs(e_f - v_filt) <= 2e-3 * v_filt, (n, e_f, v_filt)
+        else:
+            assert e_f < 1e-12, (n, e_f)
+        assert abs(e_t - v_trap) <= 2e-3 * v_trap, (n, e_t, v_trap)
+        assert abs(90.0 / k ** 2 - v_guide) <= 1e-5 * v_guide
+
+
+def test_sinconv_caption_rule_fails():
+    """The caption's K = 2N + 1 does not reproduce the printed data (the reading above)."""
+    data = _load("sinconv.txt")
+    exact = np.sin(64.0) / 16.0
+    g = lambda t: np.cos(64.0 * np.cos(t))
+    bad = 0
+    for n, v_filt, _, _ in data:
+        n = int(n)
+        e_f = abs(fourier.sin_filtered_quadrature(g, n, 2 * n + 1) - exact) / abs(exact)
+        if v_filt > 1e-12 and abs(e_f - v_filt) > 2e-3 * v_filt:
+            bad += 1
+    assert bad > 10
+
+
+def test_sinfspec_printed_values():
+    """Fig. SINFspec: |F_n| of cos(64 cos t) from 256 samples; also equal to |J_n(64)|."""
+    data = _load("sinfspec.txt")
+    t = 2 * np.pi * np.arange(256) / 256
+    c = np.fft.fft(np.cos(64 * np.cos(t))) / 256
+    for n, v in data:
+        mine = abs(c[int(n) % 256])
+        if int(n) % 2 == 0:
+            assert abs(mine - v) <= 2e-5 * v + 1e-15, (n, mine, v)   # printed roundoff ~1e-15
+            assert abs(abs(special.jv(int(n), 64.0)) - v) <= 2e-5 * v + 1e-15
+        else:          # odd n are exact zeros; the printed values there are roundoff
+            assert mine < 2e-14 and v < 2e-14
+
+
+def test_toy_exact_value():
+    """int_0^{2pi} |sin t| cos(64 cos t) dt = sin(64)/16 (Section 3.1.2)."""
+    f = lambda t: np.sin(t) * np.cos(64 * np.cos(t))
+    a, _ = integrate.quad(f, 0, np.pi, limit=2000, epsabs=1e-15)
+    assert abs(2 * a - np.sin(64) / 16) < 1e-12
+
+
+# --- closed forms --------------------------------------------------------------------------
+
+def test_sin_abs_coefficients_closed_form():
+    """F_n[|sin|] = ((-1)^n + 1) / (pi (1 - n^2)) against numerical integration (Section 3.1.3)."""
+    for n in range(-9, 10):
+        re, _ = integrate.quad(lambda t: abs(np.sin(t)) * np.cos(n * t), 0, 2 * np.pi,
+                               points=[np.pi], limit=400)
+        assert abs(re / (2 * np.pi) - fourier.sin_abs_coeff(np.array([n]))[0]) < 1e-12
+
+
+def test_spherical_functions_closed_forms():
+    x = np.linspace(0.3, 40.0, 57)
+    h = osp.sph_h1(1, x)
+    assert np.allclose(h[0], -1j * np.exp(1j * x) / x, rtol=1e-13, atol=0)
+    assert np.allclose(h[1], -np.exp(1j * x) * (x + 1j) / x ** 2, rtol=1e-13, atol=0)
+    j = osp.sph_jn(30, x)
+    y = osp.sph_yn(30, x)
+    for n in range(1, 30):
+        w = j[n] * y[n - 1] - j[n - 1] * y[n]
+        ok = np.abs(y[n]) < 1e100
+        assert np.allclose(w[ok], 1.0 / x[ok] ** 2, rtol=1e-9)
+
+
+def test_legendre_recurrence():
+    x, w = np.polynomial.legendre.leggauss(40)
+    P = osp.legendre_table(25, x)
+    gram = (P * w) @ P.T
+    assert np.allclose(gram, np.diag(2.0 / (2 * np.arange(26) + 1)), atol=1e-13)
+    assert np.allclose(osp.legendre_table(25, 1.0), 1.0)
+    assert np.allclose(osp.legendre_table(25, -1.0), (-1.0) ** np.arange(26))
+
+
+def test_gegenbauer_series_converges_to_kernel():
+    """eqn. Gegenbauer: the series reaches e^{i kappa |r + r0|}/|r + r0| (max over the angle)."""
+    err = quadrature.gegenbauer_error(7.3, 1.0, 2.0, 50)
+    assert err[50] < 1e-13
+    assert err[5] > 1e-3   # a truncated series is visibly off
+
+
+def test_plane_wave_spectrum_jacobi_anger():
+    """eqn. PlaneWaveSpec: e^{i x cos t} = sum_n i^n J_n(x) e^{i n t}."""
+    x = 9.7
+    t = 2 * np.pi * np.arange(64) / 64
+    c = np.fft.fft(np.exp(1j * x * np.cos(t))) / 64
+    n = np.arange(-20, 21)
+    assert np.allclose(c[n % 64], (1j ** n) * special.jv(n, x), atol=1e-14)
+
+
+# --- Fourier resampling ------------------------------------------------------------------
+
+def test_resample_exact_for_trig_polynomials():
+    rng = np.random.default_rng(3)
+    for n, n2 in [(12, 20), (20, 12), (16, 16), (28, 36), (36, 28)]:
+        b = min(n, n2) // 2 - 1
+        k = np.arange(-b, b + 1)
+        c = rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))
+        f = lambda t: np.exp(1j * np.outer(t, k)) @ c
+        src = f(2 * np.pi * np.arange(n) / n)
+        dst = fourier.resample_1d(src, n2)
+        assert np.allclose(dst, f(2 * np.pi * np.arange(n2) / n2), atol=1e-13)
+
+
+def test_resample_drops_nyquist_and_above():
+    n = 16
+    t = 2 * np.pi * np.arange(n) / n
+    f = np.cos(8 * t) + np.cos(7 * t)          # Nyquist and highest kept bin of 16 samples
+    out = fourier.resample_1d(f, 32)
+    t2 = 2 * np.pi * np.arange(32) / 32
+    assert np.allclose(out, np.cos(7 * t2), atol=1e-13)
+    down = fourier.resample_1d(np.cos(7 * t2), 12)   # 12 samples keep |k| <= 5
+    assert np.allclose(down, 0.0, atol=1e-13)
+
+
+# --- quadrature and transfer function ----------------------------------------------------
+
+@pytest.mark.parametrize("ka,eps", [(2.77, 1e-4), (5.5, 1e-4), (11.1, 1e-6), (22.1, 1e-4)])
+def test_quadrature_size_ratio(ka, eps):
+    """Fig. QuadSize: K / 2 (ell + 1)^2 lies in [0.6, 1.0] (asymptote 2/pi, Section 3.3.4)."""
+    q, _ = quadrature.level_quadrature(ka, 1 / np.sqrt(3), eps)
+    ratio = q.K / (2.0 * (q.ell + 1) ** 2)
+    assert 0.6 <= ratio <= 1.0
+    assert q.ntheta % 2 == 0 and np.all(q.nphi % 4 == 0)
+    assert q.nphi[0] == 4 and q.nphi[-1] == 4                   # poles (Alg. Nphi)
+    assert np.array_equal(q.nphi, q.nphi[::-1])                 # z = 0 symmetry
+
+
+def test_weights_integrate_trig_polynomials():
+    """The folded weights integrate f(theta, phi) |sin theta| ... exactly for band-limited f:
+    sum_k w_k = 4 pi^2 and sum_k w_k cos(theta_k)^2 = 2 pi^2 on the doubled torus."""
+    q = LevelQuad(6, 14, [4, 8, 12, 16, 16, 12, 8, 4])
+    w = q.weights()
+    th, ph = q.angles()
+    assert abs(w.sum() - 4 * np.pi ** 2) < 1e-12
+    assert abs(np.sum(w * np.cos(th) ** 2) - 2 * np.pi ** 2) < 1e-12
+
+
+def _single_level_errors(ka, eps, rdir, r0dir, alpha=1 / np.sqrt(3), nsamp=40, seed=0):
+    """eps_T, eps_G, eps_I of eqns. eps_T/eps_G/eps_I over random r with |r| = alpha sqrt(3)."""
+    q, _ = quadrature.level_quadrature(ka, alpha, eps)
+    r0 = 2.0 * np.asarray(r0dir, float) / np.linalg.norm(r0dir)
+    tab = transfer.transfer_table(ka, r0, q)
+    s = q.dirs()
+    w = q.weights()
+    rng = np.random.default_rng(seed)
+    dirs = rng.standard_normal((nsamp, 3)) if rdir is None else np.tile(rdir, (nsamp, 1))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    rr = alpha * np.sqrt(3.0) * dirs
+    quadv = (np.exp(1j * ka * (rr @ s.T)) * (w * tab)).sum(axis=1)
+    big = np.linalg.norm(rr + r0, axis=1)
+    exact = np.exp(1j * ka * big) / big
+    n = np.arange(q.ell + 1)
+    cosg = (rr @ r0) / (np.linalg.norm(rr, axis=1) * 2.0)
+    P = osp.legendre_table(q.ell, cosg)
+    jn = osp.sph_jn(q.ell, ka * alpha * np.sqrt(3.0))
+    hn = osp.sph_h1(q.ell, 2.0 * ka)
+    series = (1j * ka * ((-1.0) ** n) * (2 * n + 1) * hn * jn) @ P
+    e_t = np.abs(exact - quadv)
+    e_g = np.abs(exact - series)
+    return e_t, e_g, np.abs(quadv - series)
+
+
+@pytest.mark.parametrize("ka,eps", [(3.0, 1e-4), (10.0, 1e-4), (40.0, 1e-4), (10.0, 1e-8),
+                                    (40.0, 1e-8)])
+def test_single_level_integration_bound(ka, eps):
+    """Section 3.5.1: the integration error eps_I stays within ~2 eps of the target (worst cases
+    r, r0 along z and along x, plus random directions). ka = 3 at eps = 1e-8 is left out: it is in
+    the low-frequency breakdown the paper excepts."""
+    for r0dir, rdir in [((0, 0, 1), (0, 0, 1)), ((0, 0, 1), (0, 0, -1)),
+                        ((1, 0, 0), (1, 0, 0)), ((1, 0, 0), (-1, 0, 0)),
+                        ((1, 2, 2), None)]:
+        e_t, e_g, e_i = _single_level_errors(ka, eps, np.array(rdir, float) if rdir else None,
+                                             r0dir)
+        assert e_i.max() < 2.5 * eps, (ka, eps, r0dir, e_i.max())
+
+
+def test_bmtf_spectral_equals_real_space():
+    """Section 3.2: Alg. BMTF equals the real-space route -- interpolate 1/2 T from 2 ell + 1 to
+    N_theta + 2 ell - 1 samples, multiply by |sin| band-limited to that grid, anterpolate to
+    N_theta samples."""
+    ka, ell, nth = 6.0, 9, 22
+    r0 = np.array([2.0, 1.0, -2.0])
+    ncols = 8
+    spectral = transfer.bmtf(ka, r0, ell, nth, ncols,
+                             theta_rows=2 * np.pi * np.arange(nth) / nth)
+    nt = 2 * ell + 1
+    nbig = nth + 2 * ell - 1
+    thp = 2 * np.pi * np.arange(nt) / nt
+    phi = 2 * np.pi * np.arange(ncols) / ncols
+    half_t = 0.5 * transfer.transfer_eval(ka, r0, ell, transfer.sphere_dirs(thp[:, None], phi[None, :]))
+    # odd -> larger grid: all 2 ell + 1 frequencies survive
+    coef = np.fft.fft(half_t, axis=0) / nt
+    big = np.zeros((nbig, ncols), complex)
+    big[: ell + 1] = coef[: ell + 1]
+    big[nbig - ell:] = coef[nt - ell:]
+    tb = np.fft.ifft(big, axis=0) * nbig
+    m = np.arange(-(nbig // 2), nbig // 2 + 1)
+    tbig = 2 * np.pi * np.arange(nbig) / nbig
+    sband = np.real(np.exp(1j * np.outer(tbig, m)) @ fourier.sin_abs_coeff(m))
+    prod = tb * sband[:, None]
+    c2 = np.fft.fft(prod, axis=0) / nbig
+    b = nth // 2 - 1
+    small = np.zeros((nth, ncols), complex)
+    small[: b + 1] = c2[: b + 1]
+    small[nth - b:] = c2[nbig - b:]
+    real_space = np.fft.ifft(small, axis=0) * nth
+    assert np.allclose(spectral, real_space, atol=1e-11 * np.abs(spectral).max())
