@@ -1,0 +1,209 @@
+"""Throughput of the Fourier-basis FMM matvec on one MI355X.
+
+Workload: N = 2^20 points uniform on the unit sphere (seed 0), kappa = 177, leaves of at most 64
+points, complex64 charges N(0,1) (seed 1), FP32 path with eps = 1e-4. A step is one full matvec
+(gather, P2M, M2M, M2L, L2L, L2P, P2P, scatter) with the inputs resident in HBM; plan creation
+(octree, parameters, transfer tables) is setup and is reported separately. The line also carries
+the adjoint and the FP64 path (eps = 1e-6), the per-stage times, the roofline of the dominant
+stage, the error against the oracle's direct sum on a subset of targets, and that direct sum's
+own throughput on the host cores (a reported baseline, not the target).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--kappa", type=float, default=177.0)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--targets", type=int, default=2048, help="direct-sum check targets")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def stage_work(info, stage):
+    """Algorithmic work of one launch group of a stage (per right-hand side):
+    returns (bound, amount, unit) with amount in GB or TFLOP."""
+    L = info["depth"]
+    n = info["n_points"]
+    cs = 8 if info["precision"] == 1 else 16
+    if stage in ("m2l", "leaf_m2l"):
+        lv = [L] if stage == "leaf_m2l" else range(2, L + 1)
+        flops = sum(8.0 * info["n_ilist"][l] * info["K"][l] for l in lv)
+        return "alu", flops / 1e12, "TFLOP"
+    if stage in ("p2m", "l2p"):
+        return "alu", 14.0 * n * info["K"][L] / 1e12, "TFLOP"
+    if stage == "p2p":
+        return "alu", 20.0 * info["n_near_pairs"] / 1e12, "TFLOP"
+    if stage in ("m2m", "l2l"):
+        byt = sum(cs * (info["n_boxes"][l] * info["K"][l] + info["n_boxes"][l - 1] * info["K"][l - 1])
+                  for l in range(3, L + 1))
+        return "hbm", byt / 1e9, "GB"
+    if stage in ("gather", "scatter"):
+        return "hbm", (2 * cs + 8) * n / 1e9, "GB"
+    return "hbm", 0.0, "GB"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0911_4114_amd as ff
+    from paper_0911_4114_amd import workloads as wl
+
+    dev = torch.device("cuda")
+    n = args.n
+    log("generating workload n=%d" % n)
+    x = wl.sphere_points(n, seed=0)
+    q = wl.complex_normal(n, seed=1)
+    xt = torch.as_tensor(x, dtype=torch.float64, device=dev)
+    q32 = torch.as_tensor(q, dtype=torch.complex128, device=dev).to(torch.complex64)
+
+    log("plan fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = ff.Plan(xt, args.kappa, args.eps, precision="fp32")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = plan.info()
+    log("plan fp32 done in %.2fs depth=%d K=%s ell=%s" % (setup_s, info["depth"], info["K"][2:], info["ell"][2:]))
+
+    ms = timed(lambda: plan.matvec(q32), args.steps, args.warmup)
+    log("fp32 matvec %.3f ms" % ms)
+    ms_adj = timed(lambda: plan.adjoint(q32), args.steps, args.warmup)
+    log("fp32 adjoint %.3f ms" % ms_adj)
+
+    # per-stage times (separate profiled pass)
+    plan.profile(True)
+    prof_steps = max(3, min(args.steps, 10))
+    for _ in range(prof_steps):
+        plan.matvec(q32)
+    prof = plan.profile_read()
+    plan.profile(False)
+    stages = {k: {"ms_per_step": v[0] / prof_steps, "launches_per_step": v[1] / prof_steps}
+              for k, v in prof.items()}
+    cand = {k: v for k, v in stages.items() if k != "leaf_m2l"}
+    m2l_total = stages["m2l"]["ms_per_step"] + stages["leaf_m2l"]["ms_per_step"]
+    cand["m2l"] = {"ms_per_step": m2l_total,
+                   "launches_per_step": stages["m2l"]["launches_per_step"] + stages["leaf_m2l"]["launches_per_step"]}
+    dom = max(cand, key=lambda k: cand[k]["ms_per_step"])
+    bound, amount, unit = stage_work(info, dom)
+    nlaunch = max(cand[dom]["launches_per_step"], 1.0)
+    per_launch_ms = cand[dom]["ms_per_step"] / nlaunch
+    per_launch_amount = amount / nlaunch
+    if bound == "hbm":
+        achieved = per_launch_amount / (per_launch_ms * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        achieved = per_launch_amount / (per_launch_ms * 1e-3)
+        peak = FP32_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
+    roof["stage"] = dom
+    roof["launch_ms"] = per_launch_ms
+
+    # accuracy against the oracle's direct sum on a subset of targets (host FP64)
+    out = plan.matvec(q32).cpu().numpy().astype(np.complex128)
+    tg = wl.subset(n, args.targets, seed=7)
+    cpu = None
+    rel_err = None
+    if not args.no_cpu:
+        from oracle import direct
+        cores = len(os.sched_getaffinity(0))
+        log("direct sum on %d targets (%d host threads)" % (len(tg), cores))
+        t1 = time.perf_counter()
+        ref = direct.matvec(x, q, args.kappa, targets=tg)
+        cpu_s = time.perf_counter() - t1
+        rel_err = float(np.linalg.norm(out[tg] - ref) / np.linalg.norm(ref))
+        cpu = {"value": len(tg) / cpu_s / 1e6, "unit": "Mpoints/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "oracle direct sum (C/OpenMP FP64): %d of %d targets against all %d sources, %.1f s"
+                         % (len(tg), n, n, cpu_s)}
+        log("fp32 rel err %.3e; cpu %.4f Mpoints/s" % (rel_err, cpu["value"]))
+
+    fp64 = None
+    if not args.no_fp64:
+        del plan
+        torch.cuda.empty_cache()
+        log("plan fp64")
+        q64 = torch.as_tensor(q, dtype=torch.complex128, device=dev)
+        t0 = time.perf_counter()
+        p64 = ff.Plan(xt, args.kappa, 1e-6, precision="fp64")
+        torch.cuda.synchronize()
+        s64 = time.perf_counter() - t0
+        ms64 = timed(lambda: p64.matvec(q64), max(3, args.steps // 2), 2)
+        out64 = p64.matvec(q64).cpu().numpy()
+        i64 = p64.info()
+        fp64 = {"value": n / (ms64 * 1e-3) / 1e6, "ms_per_step": ms64, "setup_s": s64,
+                "depth": i64["depth"], "eps": 1e-6}
+        if not args.no_cpu:
+            fp64["rel_err"] = float(np.linalg.norm(out64[tg] - ref) / np.linalg.norm(ref))
+        log("fp64 %.3f ms err %s" % (ms64, fp64.get("rel_err")))
+
+    line = {
+        "metric": "FMM matvec Mpoints/s at rel err 1e-4 (FP32) vs 1e-6 (FP64); fwd+adjoint",
+        "value": n / (ms * 1e-3) / 1e6,
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere N=%d kappa=%g leaf<=64 FP32 eps=%g nrhs=1" % (n, args.kappa, args.eps),
+                   "n": n, "kappa": args.kappa, "eps": args.eps, "nrhs": 1,
+                   "depth": info["depth"], "ell": info["ell"][2:], "K": info["K"][2:]},
+        "rel_err": rel_err,
+        "adjoint": {"value": n / (ms_adj * 1e-3) / 1e6, "ms_per_step": ms_adj},
+        "setup_s": setup_s,
+        "stages_ms": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
+        "fp64": fp64,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

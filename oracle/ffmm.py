@@ -29,7 +29,7 @@ from .quadrature import level_quadrature, select_ell, UNIT_ROUNDOFF
 from .transfer import transfer_table
 from .resample import resample_sig
 
-ALPHA_DEFAULT = 1.0 / np.sqrt(3.0)
+ALPHA_DEFAULT = 0.8
 EPS_SAFETY_DEFAULT = 0.1
 
 

@@ -96,34 +96,49 @@ def ell_search_max(ka, r):
 
 # Unit roundoff of the arithmetic the signatures are carried in.
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
-# The rounding floor below is a coherent worst case; the oracle's measured breakdown at
-# ka = pi in FP64 sits 5-8x under it, so a quarter of it is used.
+# The transfer-function part of the floor below is a coherent worst case; the oracle's measured
+# breakdown at ka = pi in FP64 sits 5-8x under it, so a quarter of it is used.
 FLOOR_SCALE = 0.25
 
 
 def rounding_floor(ka, r0, ell_max, u):
     """Rounding floor of the low-frequency breakdown (Sections 2.1 and 3.5.1: for n > x the
-    Hankel function diverges, the transfer function becomes huge and roundoff dominates). The
-    integral of |T_ell| over the sphere is at most ka sum_{n<=ell} (2n+1) |h_n(ka |r0|)| (box
-    units), and the far field is recovered from it by cancellation, so u times that integral,
-    scaled by FLOOR_SCALE, is the floor. Returns [ell_max + 1]."""
+    Hankel function diverges, the transfer function becomes huge and roundoff dominates), box
+    units, for ell = 0..ell_max. Two parts:
+    * evaluating T_ell (always in FP64) sums terms up to |c_n|, c_n = (i ka / 4 pi) i^n (2n+1) h_n;
+      its error, integrated over the sphere, is at most u64 * ka * sum (2n+1) |h_n(ka |r0|)|
+      (scaled by FLOOR_SCALE);
+    * the signature arithmetic in the plan's precision u rounds every one of the ~(4/pi)(ell+1)^2
+      quadrature terms independently; their random-walk sum is u * ka * sqrt(sum (2n+1) |h_n|^2 / K)
+      (the L2 norm of T from the orthogonality of the P_n)."""
     n = np.arange(ell_max + 1)
     h = np.abs(sph_h1(ell_max, ka * r0))
-    return FLOOR_SCALE * u * ka * np.cumsum((2 * n + 1) * h)
+    coherent = FLOOR_SCALE * UNIT_ROUNDOFF["fp64"] * ka * np.cumsum((2 * n + 1) * h)
+    kq = (4.0 / np.pi) * (n + 1.0) ** 2
+    walk = u * ka * np.sqrt(np.cumsum((2 * n + 1) * h * h) / kq)
+    return coherent + walk
+
+
+# Radius used to balance truncation against the rounding floor in the low-frequency breakdown:
+# the box size, |r| = a (alpha = 1/sqrt(3), the value of Fig. GegError).
+R_BREAKDOWN = 1.0
 
 
 def select_ell(ka, r, r0, eps, u=UNIT_ROUNDOFF["fp64"]):
-    """Section 2.1: the smallest ell whose predicted error max_gamma |eps_G| + rounding floor is
-    below eps. If no ell reaches eps (low-frequency breakdown, Section 3.5.1), the ell with the
-    smallest predicted error is returned. Returns (ell, predicted error)."""
+    """Section 2.1: the smallest ell whose predicted error max_gamma |eps_G(ell; r)| + rounding
+    floor is below eps. If no ell reaches eps (low-frequency breakdown, Section 3.5.1), the
+    achievable accuracy is set by roundoff: ell then minimises the truncation error at
+    |r| = R_BREAKDOWN plus the floor. Returns (ell, predicted error)."""
     emax = ell_search_max(ka, r)
-    tot = gegenbauer_error(ka, r, r0, emax) + rounding_floor(ka, r0, emax, u)
+    floor = rounding_floor(ka, r0, emax, u)
+    tot = gegenbauer_error(ka, r, r0, emax) + floor
     ok = np.nonzero(tot[1:] < eps)[0]
     if len(ok):
         ell = int(ok[0]) + 1
-    else:
-        ell = int(np.argmin(tot[1:])) + 1
-    return ell, float(tot[ell])
+        return ell, float(tot[ell])
+    low = gegenbauer_error(ka, min(r, R_BREAKDOWN), r0, emax) + floor
+    ell = int(np.argmin(low[1:])) + 1
+    return ell, float(low[ell])
 
 
 def select_ntheta(ka, r, r0, ell, eps):

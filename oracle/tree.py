@@ -12,12 +12,18 @@ Readings of what the paper leaves open:
 * Leaf index per axis: min(floor((x - lo) * (2^L / S)), 2^L - 1), in FP64, with the factor
   2^L / S computed first.
 * Morton key: bit b of the x index goes to bit 3b, of y to 3b + 1, of z to 3b + 2. Points are
-  stably sorted by key (ties keep the input order).
+  stably sorted by their key at the finest resolution, 21 bits per axis (ties keep the input
+  order); the key of a depth-L leaf is that key shifted right by 3 (21 - L) bits. Because the
+  factor 2^21 / S is 2^(21 - L) times 2^L / S exactly, the shifted fine index equals the depth-L
+  index above.
 * Only occupied boxes exist; empty boxes contribute nothing to any sum.
 * Depth (when not given): the smallest L >= 2 whose fullest leaf holds <= max_leaf points.
 * List order: every neighbour / interaction list is sorted by source box index (Morton order).
 """
 import numpy as np
+
+
+MAX_DEPTH = 21
 
 
 def root_cube(x):
@@ -121,7 +127,9 @@ class Tree:
         self.lo, self.side = root_cube(x)
         self.idx = quantize(x, self.lo, self.side, depth)
         self.leaf_key = morton(self.idx, depth)
-        self.perm = np.argsort(self.leaf_key, kind="stable")
+        self.fine_key = morton(quantize(x, self.lo, self.side, MAX_DEPTH), MAX_DEPTH)
+        assert np.array_equal(self.fine_key >> np.uint64(3 * (MAX_DEPTH - depth)), self.leaf_key)
+        self.perm = np.argsort(self.fine_key, kind="stable")
         self.sorted_keys = self.leaf_key[self.perm]
         self.xs = x[self.perm]
         self.levels = {}

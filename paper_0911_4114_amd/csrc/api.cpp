@@ -1,0 +1,454 @@
+// C ABI of the library (include/ffmm.h): argument checks, plan assembly and inspection calls.
+// No exception crosses this boundary; failures become an ffmm_status plus a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace ffmm {
+
+static thread_local std::string g_last_error;
+
+void fail(ffmm_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void* DeviceArena::alloc(size_t nbytes)
+{
+    void* p = nullptr;
+    if (nbytes == 0) nbytes = 16;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? FFMM_ERR_OUT_OF_MEMORY : FFMM_ERR_HIP,
+             std::string("hipMalloc of ") + std::to_string(nbytes) + " bytes failed: " +
+                 hipGetErrorString(e));
+    }
+    ptrs.push_back(p);
+    bytes += nbytes;
+    return p;
+}
+
+void DeviceArena::release()
+{
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+}
+
+void prepare_rel(ffmm_plan* p, hipStream_t s);
+
+StageScope::StageScope(ffmm_plan* plan, int st, hipStream_t stream) : p(plan), stage(st), s(stream)
+{
+    if (!p->profile) return;
+    FFMM_HIP(hipEventCreate(&a));
+    FFMM_HIP(hipEventCreate(&b));
+    FFMM_HIP(hipEventRecord(a, s));
+}
+
+StageScope::~StageScope() noexcept(false)
+{
+    if (!a) return;
+    if (std::uncaught_exceptions()) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return;
+    }
+    FFMM_HIP(hipEventRecord(b, s));
+    p->events.push_back({stage, a, b});
+}
+
+static void drain_events(ffmm_plan* p, bool accumulate)
+{
+    for (auto& e : p->events) {
+        if (accumulate) {
+            FFMM_HIP(hipEventSynchronize(e.b));
+            float ms = 0.0f;
+            FFMM_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+            p->prof_ms[e.stage] += ms;
+            p->prof_calls[e.stage] += 1;
+        }
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    p->events.clear();
+}
+
+template <class F>
+static ffmm_status guarded(F&& f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return FFMM_OK;
+    } catch (const Error& e) {
+        g_last_error = e.message;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return FFMM_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return FFMM_ERR_INTERNAL;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return FFMM_ERR_INTERNAL;
+    }
+}
+
+static size_t csize(const ffmm_plan* p) { return p->prec == FFMM_FP32 ? 8 : 16; }
+
+static void allocate_workspaces(ffmm_plan* p)
+{
+    const int mr = p->opt.max_rhs;
+    const size_t cs = csize(p);
+    for (int l = 2; l <= p->depth; ++l) {
+        LevelData& L = p->lev[l];
+        L.sigM = p->arena.alloc(cs * (size_t)mr * L.n * L.K);
+        L.sigL = p->arena.alloc(cs * (size_t)mr * L.n * L.K);
+    }
+    size_t s1 = 1, s2 = 1;
+    for (int l = 3; l <= p->depth; ++l) {
+        const Resampler& rs = p->up[l];
+        const int64_t nb = p->lev[l].n;
+        s1 = std::max(s1, (size_t)nb * rs.rows_src * rs.nphi_all);
+        s2 = std::max(s2, (size_t)nb * (rs.nphi_all / 2) * rs.nt_dst);
+    }
+    for (int l = 2; l < p->depth; ++l) {
+        const Resampler& rs = p->down[l];
+        const int64_t nb = p->lev[l + 1].n;
+        s1 = std::max(s1, (size_t)nb * rs.rows_src * rs.nphi_all);
+        s2 = std::max(s2, (size_t)nb * (rs.nphi_all / 2) * rs.nt_dst);
+    }
+    p->scratch1_bytes = cs * s1 * mr;
+    p->scratch2_bytes = cs * s2 * mr;
+    p->scratch1 = p->arena.alloc(p->scratch1_bytes);
+    p->scratch2 = p->arena.alloc(p->scratch2_bytes);
+    p->qs = p->arena.alloc(cs * (size_t)mr * p->n);
+    p->phis = p->arena.alloc(cs * (size_t)mr * p->n * 3);
+}
+
+}  // namespace ffmm
+
+using namespace ffmm;
+
+extern "C" {
+
+ffmm_status ffmm_options_default(ffmm_options* o)
+{
+    if (!o) {
+        g_last_error = "options pointer is NULL";
+        return FFMM_ERR_INVALID_ARG;
+    }
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = (int32_t)sizeof(ffmm_options);
+    o->precision = FFMM_FP64;
+    o->max_leaf_points = 64;
+    o->depth = 0;
+    o->alpha = 0.8;
+    o->eps_safety = 0.1;
+    o->max_rhs = 1;
+    o->reduce_depth = 1;
+    g_last_error.clear();
+    return FFMM_OK;
+}
+
+ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, double eps,
+                             const ffmm_options* o, void* hip_stream, ffmm_plan** out)
+{
+    ffmm_plan* p = nullptr;
+    ffmm_status st = guarded([&] {
+        if (!out) fail(FFMM_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (!d_points) fail(FFMM_ERR_INVALID_ARG, "points pointer is NULL");
+        if (n < 1) fail(FFMM_ERR_INVALID_ARG, "n must be >= 1");
+        if (n > (int64_t)INT32_MAX - 1) fail(FFMM_ERR_UNSUPPORTED, "n exceeds 2^31 - 2");
+        if (!std::isfinite(kappa) || kappa <= 0.0) fail(FFMM_ERR_INVALID_ARG, "kappa must be finite and > 0");
+        if (!std::isfinite(eps) || eps < 1e-12 || eps > 0.5)
+            fail(FFMM_ERR_INVALID_ARG, "eps must lie in [1e-12, 0.5]");
+        ffmm_options opt;
+        ffmm_options_default(&opt);
+        if (o) {
+            if (o->struct_size != (int32_t)sizeof(ffmm_options))
+                fail(FFMM_ERR_INVALID_ARG, "options.struct_size does not match this library");
+            opt = *o;
+        }
+        if (opt.precision != FFMM_FP64 && opt.precision != FFMM_FP32)
+            fail(FFMM_ERR_INVALID_ARG, "unknown precision");
+        if (opt.precision == FFMM_FP32 && eps < 1e-7)
+            fail(FFMM_ERR_UNSUPPORTED, "FP32 plans need eps >= 1e-7");
+        if (opt.depth != 0 && (opt.depth < 2 || opt.depth > kMaxDepth))
+            fail(FFMM_ERR_INVALID_ARG, "depth must be 0 or in [2, 21]");
+        if (opt.depth == 0 && opt.max_leaf_points < 1) fail(FFMM_ERR_INVALID_ARG, "max_leaf_points must be >= 1");
+        if (!(opt.alpha > 0.0 && opt.alpha <= 1.0)) fail(FFMM_ERR_INVALID_ARG, "alpha must lie in (0, 1]");
+        if (!(opt.eps_safety > 0.0 && opt.eps_safety <= 1.0))
+            fail(FFMM_ERR_INVALID_ARG, "eps_safety must lie in (0, 1]");
+        if (opt.max_rhs < 1 || opt.max_rhs > 65535) fail(FFMM_ERR_INVALID_ARG, "max_rhs must lie in [1, 65535]");
+        for (int l = 0; l < FFMM_MAX_LEVELS; ++l)
+            if (opt.ell_override[l] < 0 || opt.ell_override[l] > 2000)
+                fail(FFMM_ERR_INVALID_ARG, "ell_override out of range");
+        int ndev = 0;
+        FFMM_HIP(hipGetDeviceCount(&ndev));
+        if (ndev < 1) fail(FFMM_ERR_HIP, "no HIP device");
+        hipStream_t s = (hipStream_t)hip_stream;
+        p = new ffmm_plan();
+        p->n = n;
+        p->kappa = kappa;
+        p->eps = eps;
+        p->opt = opt;
+        p->prec = opt.precision;
+        build_tree(p, d_points, s);
+        build_tables(p, s);
+        prepare_rel(p, s);
+        allocate_workspaces(p);
+        FFMM_HIP(hipStreamSynchronize(s));
+        *out = p;
+    });
+    if (st != FFMM_OK && p) {
+        (void)hipDeviceSynchronize();
+        p->arena.release();
+        delete p;
+    }
+    return st;
+}
+
+static void check_call(ffmm_plan* plan, const void* in, void* out, int32_t nrhs)
+{
+    if (!plan) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+    if (!in || !out) fail(FFMM_ERR_INVALID_ARG, "input or output pointer is NULL");
+    if (in == out) fail(FFMM_ERR_INVALID_ARG, "input and output must not alias");
+    if (nrhs < 1 || nrhs > plan->opt.max_rhs)
+        fail(FFMM_ERR_INVALID_ARG, "nrhs must lie in [1, max_rhs] (max_rhs = " +
+                                       std::to_string(plan->opt.max_rhs) + ")");
+}
+
+ffmm_status ffmm_matvec_stages(ffmm_plan* plan, const void* d_q, void* d_phi, int32_t nrhs,
+                               int32_t stages, void* hip_stream)
+{
+    return guarded([&] {
+        check_call(plan, d_q, d_phi, nrhs);
+        if (stages < 1 || stages > FFMM_STAGE_ALL) fail(FFMM_ERR_INVALID_ARG, "bad stage mask");
+        run_matvec(plan, d_q, d_phi, nrhs, stages, false, false, (hipStream_t)hip_stream);
+        plan->has_run = true;
+    });
+}
+
+ffmm_status ffmm_matvec(ffmm_plan* plan, const void* d_q, void* d_phi, int32_t nrhs, void* hip_stream)
+{
+    return ffmm_matvec_stages(plan, d_q, d_phi, nrhs, FFMM_STAGE_ALL, hip_stream);
+}
+
+ffmm_status ffmm_adjoint(ffmm_plan* plan, const void* d_g, void* d_out, int32_t nrhs, void* hip_stream)
+{
+    return guarded([&] {
+        check_call(plan, d_g, d_out, nrhs);
+        run_matvec(plan, d_g, d_out, nrhs, FFMM_STAGE_ALL, true, false, (hipStream_t)hip_stream);
+        plan->has_run = true;
+    });
+}
+
+ffmm_status ffmm_field_gradient(ffmm_plan* plan, const void* d_q, void* d_grad, int32_t nrhs,
+                                void* hip_stream)
+{
+    return guarded([&] {
+        check_call(plan, d_q, d_grad, nrhs);
+        run_matvec(plan, d_q, d_grad, nrhs, FFMM_STAGE_ALL, false, true, (hipStream_t)hip_stream);
+        plan->has_run = true;
+    });
+}
+
+ffmm_status ffmm_plan_info_get(const ffmm_plan* p, ffmm_plan_info* out)
+{
+    return guarded([&] {
+        if (!p || !out) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        out->depth = p->depth;
+        out->precision = p->prec;
+        out->n_points = p->n;
+        out->kappa = p->kappa;
+        out->eps = p->eps;
+        for (int a = 0; a < 3; ++a) out->root_lo[a] = p->lo[a];
+        out->root_side = p->side;
+        for (int l = 0; l <= p->depth; ++l) {
+            const LevelData& L = p->lev[l];
+            out->n_boxes[l] = L.n;
+            if (l >= 2) {
+                out->ell[l] = L.par.ell;
+                out->ntheta[l] = L.par.ntheta;
+                out->nphi_max[l] = *std::max_element(L.par.nphi.begin(), L.par.nphi.end());
+                out->K[l] = L.K;
+                out->n_ilist[l] = L.n_il;
+                out->predicted_err[l] = p->predicted[l];
+            }
+        }
+        out->n_near_pairs = p->near_pairs;
+        out->device_bytes = (int64_t)p->arena.bytes;
+        out->max_rhs = p->opt.max_rhs;
+    });
+}
+
+ffmm_status ffmm_profile_enable(ffmm_plan* p, int32_t on)
+{
+    return guarded([&] {
+        if (!p) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        p->profile = on != 0;
+    });
+}
+
+ffmm_status ffmm_profile_read(ffmm_plan* p, double* ms, int64_t* calls)
+{
+    return guarded([&] {
+        if (!p) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        drain_events(p, true);
+        for (int i = 0; i < FFMM_PROF_NUM; ++i) {
+            if (ms) ms[i] = p->prof_ms[i];
+            if (calls) calls[i] = p->prof_calls[i];
+            p->prof_ms[i] = 0.0;
+            p->prof_calls[i] = 0;
+        }
+    });
+}
+
+ffmm_status ffmm_plan_destroy(ffmm_plan* p)
+{
+    return guarded([&] {
+        if (!p) return;
+        (void)hipDeviceSynchronize();
+        drain_events(p, false);
+        p->arena.release();
+        delete p;
+    });
+}
+
+const char* ffmm_status_string(ffmm_status s)
+{
+    switch (s) {
+    case FFMM_OK: return "ok";
+    case FFMM_ERR_INVALID_ARG: return "invalid argument";
+    case FFMM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case FFMM_ERR_HIP: return "HIP runtime error";
+    case FFMM_ERR_UNSUPPORTED: return "unsupported";
+    case FFMM_ERR_ACCURACY: return "accuracy target unreachable";
+    case FFMM_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* ffmm_last_error_message(void) { return g_last_error.c_str(); }
+
+ffmm_status ffmm_select_level_params(double ka, double alpha, double eps, int32_t precision,
+                                     int32_t ell_in, int32_t* ell, int32_t* ntheta, int32_t* nphi,
+                                     int32_t nphi_cap, double* predicted)
+{
+    return guarded([&] {
+        if (!ell || !ntheta || !nphi) fail(FFMM_ERR_INVALID_ARG, "NULL output");
+        if (!(ka > 0.0) || !std::isfinite(ka)) fail(FFMM_ERR_INVALID_ARG, "ka must be finite and > 0");
+        if (!(alpha > 0.0 && alpha <= 1.0)) fail(FFMM_ERR_INVALID_ARG, "alpha must lie in (0, 1]");
+        if (!(eps > 0.0) || !std::isfinite(eps)) fail(FFMM_ERR_INVALID_ARG, "eps must be > 0");
+        if (precision != FFMM_FP64 && precision != FFMM_FP32) fail(FFMM_ERR_INVALID_ARG, "precision");
+        if (ell_in < 0 || ell_in > 2000) fail(FFMM_ERR_INVALID_ARG, "ell_in out of range");
+        LevelParams lp;
+        level_params(ka, alpha, eps, precision == FFMM_FP32 ? kUnitRoundoffFP32 : kUnitRoundoffFP64,
+                     ell_in, &lp);
+        if ((int)lp.nphi.size() > nphi_cap) fail(FFMM_ERR_INVALID_ARG, "nphi_cap too small");
+        *ell = lp.ell;
+        *ntheta = lp.ntheta;
+        for (size_t i = 0; i < lp.nphi.size(); ++i) nphi[i] = lp.nphi[i];
+        if (predicted) *predicted = lp.predicted;
+    });
+}
+
+ffmm_status ffmm_plan_get_perm(const ffmm_plan* p, int64_t* perm)
+{
+    return guarded([&] {
+        if (!p || !perm) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        FFMM_HIP(hipDeviceSynchronize());
+        FFMM_HIP(hipMemcpy(perm, p->perm, sizeof(int64_t) * p->n, hipMemcpyDeviceToHost));
+    });
+}
+
+ffmm_status ffmm_plan_get_level(const ffmm_plan* p, int32_t l, uint64_t* keys, int32_t* parent,
+                                int32_t* start, int32_t* count, int32_t* il_ptr, int32_t* il_src,
+                                int32_t* il_code, int32_t* nb_ptr, int32_t* nb_src)
+{
+    return guarded([&] {
+        if (!p) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        if (l < 0 || l > p->depth) fail(FFMM_ERR_INVALID_ARG, "level out of range");
+        const LevelData& L = p->lev[l];
+        FFMM_HIP(hipDeviceSynchronize());
+        auto cp = [](void* dst, const void* src, size_t bytes) {
+            if (dst && src && bytes) FFMM_HIP(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        };
+        cp(keys, L.keys, sizeof(uint64_t) * L.n);
+        if (l >= 1) cp(parent, L.parent, sizeof(int32_t) * L.n);
+        if (l == p->depth) {
+            cp(start, p->leaf_start, sizeof(int32_t) * L.n);
+            cp(count, p->leaf_count, sizeof(int32_t) * L.n);
+            cp(nb_ptr, p->nb_ptr, sizeof(int32_t) * (L.n + 1));
+            cp(nb_src, p->nb_src, sizeof(int32_t) * p->n_nb);
+        }
+        if (l >= 2) {
+            cp(il_ptr, L.il_ptr, sizeof(int32_t) * (L.n + 1));
+            cp(il_src, L.il_src, sizeof(int32_t) * L.n_il);
+            cp(il_code, L.il_code, sizeof(int32_t) * L.n_il);
+        }
+    });
+}
+
+ffmm_status ffmm_plan_get_nphi(const ffmm_plan* p, int32_t l, int32_t* nphi)
+{
+    return guarded([&] {
+        if (!p || !nphi) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        if (l < 2 || l > p->depth) fail(FFMM_ERR_INVALID_ARG, "level out of range");
+        const LevelData& L = p->lev[l];
+        for (int i = 0; i < L.nrows; ++i) nphi[i] = L.par.nphi[i];
+    });
+}
+
+static void copy_complex_to_f64(const ffmm_plan* p, const void* src, size_t count, double* out)
+{
+    FFMM_HIP(hipDeviceSynchronize());
+    if (p->prec == FFMM_FP64) {
+        FFMM_HIP(hipMemcpy(out, src, 16 * count, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(2 * count);
+        FFMM_HIP(hipMemcpy(tmp.data(), src, 8 * count, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < 2 * count; ++i) out[i] = tmp[i];
+    }
+}
+
+ffmm_status ffmm_plan_get_transfer(const ffmm_plan* p, int32_t l, int32_t code, double* out)
+{
+    return guarded([&] {
+        if (!p || !out) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        if (l < 2 || l > p->depth) fail(FFMM_ERR_INVALID_ARG, "level out of range");
+        if (code < 0 || code >= kNumCodes) fail(FFMM_ERR_INVALID_ARG, "code out of range");
+        int32_t map[kNumCodes];
+        offset_code_map(map);
+        if (map[code] < 0) fail(FFMM_ERR_INVALID_ARG, "inner offset code has no transfer function");
+        const LevelData& L = p->lev[l];
+        const char* base = (const char*)L.transfer + csize(p) * (size_t)map[code] * L.K;
+        copy_complex_to_f64(p, base, L.K, out);
+    });
+}
+
+ffmm_status ffmm_plan_get_signature(const ffmm_plan* p, int32_t kind, int32_t l, int32_t rhs,
+                                    double* out)
+{
+    return guarded([&] {
+        if (!p || !out) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        if (l < 2 || l > p->depth) fail(FFMM_ERR_INVALID_ARG, "level out of range");
+        if (kind != 0 && kind != 1) fail(FFMM_ERR_INVALID_ARG, "kind must be 0 (M) or 1 (L)");
+        if (rhs < 0 || rhs >= p->opt.max_rhs) fail(FFMM_ERR_INVALID_ARG, "rhs out of range");
+        if (!p->has_run) fail(FFMM_ERR_INVALID_ARG, "no matvec has run on this plan");
+        const LevelData& L = p->lev[l];
+        const void* sig = kind == 0 ? L.sigM : L.sigL;
+        const char* base = (const char*)sig + csize(p) * (size_t)rhs * L.n * L.K;
+        copy_complex_to_f64(p, base, (size_t)L.n * L.K, out);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// Internal declarations of the MI355X Fourier-basis FMM library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ffmm.h"
+#include "params.hpp"
+
+namespace ffmm {
+
+// Errors inside the library are C++ exceptions of this type; the C ABI turns them into a status.
+struct Error {
+    ffmm_status status;
+    std::string message;
+};
+[[noreturn]] void fail(ffmm_status st, const std::string& msg);
+
+#define FFMM_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            ::ffmm::fail(FFMM_ERR_HIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FFMM_LAUNCH_CHECK() FFMM_HIP(hipGetLastError())
+
+constexpr int kMaxDepth = 21;        // bits per axis of the Morton keys
+constexpr int kNumOffsets = 316;     // transfer vectors per level (Section 3.2)
+constexpr int kNumCodes = 343;       // 7^3 offset codes, inner 3^3 unused
+
+// Device allocations owned by a plan.
+struct DeviceArena {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    void* alloc(size_t nbytes);
+    template <class T>
+    T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+    void release();
+};
+
+// One level of the octree with its quadrature and tables.
+struct LevelData {
+    int l = 0;
+    int64_t n = 0;            // occupied boxes
+    double a = 0.0;           // box side
+    uint64_t* keys = nullptr; // Morton keys, ascending
+    int32_t* parent = nullptr;      // index in level l-1
+    int32_t* octant = nullptr;      // position inside the parent, 0..7 (x + 2y + 4z)
+    int32_t* child_start = nullptr; // children in level l+1 are contiguous
+    int32_t* child_count = nullptr;
+    double* centers = nullptr;      // [n][3]
+    // interaction list (levels >= 2)
+    int64_t n_il = 0;
+    int32_t* il_ptr = nullptr;      // [n+1]
+    int32_t* il_src = nullptr;      // [n_il]
+    int32_t* il_code = nullptr;     // [n_il] offset code 0..342
+    int32_t* il_tix = nullptr;      // [n_il] transfer table row 0..315
+    // quadrature (levels >= 2)
+    LevelParams par;
+    int K = 0;
+    int nrows = 0;
+    std::vector<int> row_off;       // host [nrows+1]
+    int32_t* d_row_off = nullptr;
+    int32_t* d_nphi = nullptr;
+    void* dirs = nullptr;           // [K][3] real
+    void* weights = nullptr;        // [K] real (leaf level)
+    void* transfer = nullptr;       // [316][K] complex
+    void* trans = nullptr;          // [8][K] complex: e^{i kappa s.(oct - 1/2) a_{l+1}} (l < L)
+    void* sigM = nullptr;           // [max_rhs][n][K] complex
+    void* sigL = nullptr;           // [max_rhs][n][K] complex
+};
+
+// Dense real Fourier-resample operators between two level quadratures (Section 3.4).
+struct Resampler {
+    int nphi_all = 0;               // largest row length of both quadratures
+    int nt_src = 0, nt_dst = 0;
+    int rows_src = 0, rows_dst = 0;
+    int K_src = 0, K_dst = 0;
+    void* d1 = nullptr;             // step 1, per source row n: [N_phi,n][nphi_all] (j fastest)
+    void* dth = nullptr;            // step 3: [nt_src][nt_dst] (t' fastest)
+    void* d5 = nullptr;             // step 5, per dest row n': [nphi_all][N'_phi,n'] (j' fastest)
+    int32_t* d_src_row_off = nullptr;
+    int32_t* d_src_nphi = nullptr;
+    int32_t* d_dst_row_off = nullptr;
+    int32_t* d_dst_nphi = nullptr;
+    int32_t* d_dst_row_of_k = nullptr; // [K_dst] row of each destination sample
+};
+
+}  // namespace ffmm
+
+struct ffmm_plan {
+    int64_t n = 0;
+    double kappa = 0.0, eps = 0.0;
+    ffmm_options opt{};
+    int prec = FFMM_FP64;
+    int depth = 0;
+    double lo[3] = {0, 0, 0};
+    double side = 1.0;
+    ffmm::DeviceArena arena;
+    int64_t* perm = nullptr;        // [n] caller index of each Morton-ordered point
+    double* xs = nullptr;           // [n][3] sorted coordinates (FP64)
+    void* rel = nullptr;            // [n][3] coordinates minus leaf centre (plan precision)
+    int32_t* point_box = nullptr;   // [n] leaf box of each sorted point
+    int32_t* leaf_start = nullptr;  // [nL]
+    int32_t* leaf_count = nullptr;  // [nL]
+    int32_t* nb_ptr = nullptr;      // leaf neighbour list CSR
+    int32_t* nb_src = nullptr;
+    int64_t n_nb = 0;
+    int64_t near_pairs = 0;
+    int max_leaf_count = 0;
+    std::vector<ffmm::LevelData> lev;       // 0..depth
+    std::vector<ffmm::Resampler> up;        // up[l]: level l -> l-1 (l = 3..L)
+    std::vector<ffmm::Resampler> down;      // down[l]: level l -> l+1 (l = 2..L-1)
+    void* qs = nullptr;             // [max_rhs][n] complex, sorted charges
+    void* phis = nullptr;           // [max_rhs][n] complex (or [max_rhs][n][3] for gradients)
+    void* scratch1 = nullptr;       // resample workspaces
+    void* scratch2 = nullptr;
+    size_t scratch1_bytes = 0, scratch2_bytes = 0;
+    std::vector<double> predicted;  // per level
+    bool has_run = false;
+    // stage timing (ffmm_profile_enable)
+    bool profile = false;
+    struct EventPair {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<EventPair> events;
+    double prof_ms[16] = {0};
+    int64_t prof_calls[16] = {0};
+};
+
+namespace ffmm {
+
+void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s);
+void build_tables(ffmm_plan* p, hipStream_t s);
+void run_matvec(ffmm_plan* p, const void* q, void* out, int nrhs, int stages, bool conj_io,
+                bool gradient, hipStream_t s);
+
+// Records a HIP event pair around a stage when the plan profiles (no-op otherwise).
+struct StageScope {
+    ffmm_plan* p;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageScope(ffmm_plan* plan, int st, hipStream_t stream);
+    ~StageScope() noexcept(false);
+};
+
+// map offset code (0..342) -> transfer table row (0..315), -1 for the inner 27 codes
+void offset_code_map(int32_t* map);
+
+// exclusive prefix sum of n int32 values; returns the total (synchronises the stream)
+int64_t exclusive_scan(DeviceArena& tmp, const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+
+}  // namespace ffmm

@@ -1,0 +1,428 @@
+// Plan-time tables of every level (FP64 arithmetic; stored in the plan precision):
+//  * level quadrature (Section 3.4): rows theta_n = 2 pi n / N_theta, n = 0..N_theta/2, row n with
+//    N_phi(theta_n) samples at phi_m = 2 pi m / N_phi(theta_n); s = [cos phi sin theta,
+//    sin phi sin theta, cos theta]; leaf weights 4 pi^2 / (N_theta N_phi(theta_n)), doubled for
+//    the interior rows because each also stands for row N_theta - n (eqn. eps_T folded onto the
+//    stored half, eqn. NumSphereSym);
+//  * band-limited modified transfer functions T^{s,LL} of the 316 transfer vectors (Alg. BMTF,
+//    Section 3.2, then the per-row phi anterpolation of Section 3.3.2), computed on the GPU;
+//  * translation tables e^{i kappa s.(c_child - c_parent)} for the 8 child octants;
+//  * the real Fourier-resample operators of the five-step inter/anterpolation (Section 3.4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace ffmm {
+
+namespace {
+
+using cd = std::complex<double>;
+constexpr double kPi = 3.14159265358979323846;
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// A[ob][j][m] = 1/2 sum_n c_n P_n(s(theta'_j, phi_m) . r0hat), theta'_j = 2 pi j / (2 ell + 1),
+// phi_m = 2 pi m / ncols (eqn. TransferFn; the 1/2 of T^s = 1/2 T |sin|).
+__global__ void bmtf_sample(int nb, int ell, int ncols, const double2* __restrict__ cn,
+                            const double* __restrict__ r0hat, double2* __restrict__ A)
+{
+    const int nt = 2 * ell + 1;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * nt * ncols;
+    if (idx >= total) return;
+    const int m = (int)(idx % ncols);
+    const int j = (int)((idx / ncols) % nt);
+    const int ob = (int)(idx / ((int64_t)ncols * nt));
+    double st, ct, sp, cp;
+    sincospi(2.0 * j / nt, &st, &ct);
+    sincospi(2.0 * m / ncols, &sp, &cp);
+    const double* rh = r0hat + 3 * ob;
+    double t = cp * st * rh[0] + sp * st * rh[1] + ct * rh[2];
+    t = fmin(1.0, fmax(-1.0, t));
+    const double2* c = cn + (int64_t)ob * (ell + 1);
+    double p0 = 1.0, p1 = t;
+    double re = c[0].x, im = c[0].y;
+    if (ell >= 1) {
+        re += c[1].x * p1;
+        im += c[1].y * p1;
+    }
+    for (int n = 1; n < ell; ++n) {
+        double p2 = ((2.0 * n + 1.0) * t * p1 - n * p0) / (n + 1.0);
+        re += c[n + 1].x * p2;
+        im += c[n + 1].y * p2;
+        p0 = p1;
+        p1 = p2;
+    }
+    A[idx] = make_double2(0.5 * re, 0.5 * im);
+}
+
+// TL[ob][n][m] = sum_j B[n][j] A[ob][j][m]: theta Fourier coefficients of the samples, convolved
+// with the |sin| coefficients, truncated to |k| <= N_theta/2 - 1 and evaluated at theta_n; the
+// three linear steps of Alg. BMTF folded into the real matrix B (host).
+__global__ void bmtf_theta(int nb, int nt, int rows, int ncols, const double* __restrict__ B,
+                           const double2* __restrict__ A, double2* __restrict__ TL)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * rows * ncols;
+    if (idx >= total) return;
+    const int m = (int)(idx % ncols);
+    const int n = (int)((idx / ncols) % rows);
+    const int ob = (int)(idx / ((int64_t)ncols * rows));
+    const double2* a = A + (int64_t)ob * nt * ncols + m;
+    const double* b = B + (int64_t)n * nt;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < nt; ++j) {
+        double2 v = a[(int64_t)j * ncols];
+        re += b[j] * v.x;
+        im += b[j] * v.y;
+    }
+    TL[idx] = make_double2(re, im);
+}
+
+// Per row: phi Fourier coefficients c_mu, |mu| <= ncols/2 - 1, of the ncols samples
+// (tw[t] = e^{-2 pi i t / ncols}). Cf[ob][n][mu + ncols/2 - 1].
+__global__ void bmtf_phi_coef(int nb, int rows, int ncols, const double2* __restrict__ tw,
+                              const double2* __restrict__ TL, double2* __restrict__ Cf)
+{
+    const int nc = ncols - 1;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * rows * nc;
+    if (idx >= total) return;
+    const int mu = (int)(idx % nc) - (ncols / 2 - 1);
+    const int64_t rowid = idx / nc;
+    const double2* row = TL + rowid * ncols;
+    double cr = 0.0, ci = 0.0;
+    for (int m = 0; m < ncols; ++m) {
+        long t = ((long)mu * m) % ncols;
+        if (t < 0) t += ncols;
+        double2 w = tw[t];
+        double2 v = row[m];
+        cr += v.x * w.x - v.y * w.y;
+        ci += v.x * w.y + v.y * w.x;
+    }
+    Cf[idx] = make_double2(cr / ncols, ci / ncols);
+}
+
+// Each row evaluated at its own N_phi(theta_n) points keeping |mu| <= min(ncols, N_phi)/2 - 1
+// (Section 3.3.2: the anterpolation from the full column count to N_phi(theta_n)).
+__global__ void bmtf_phi_eval(int nb, int rows, int ncols, int K, const int32_t* __restrict__ row_off,
+                              const int32_t* __restrict__ nphi, const int32_t* __restrict__ row_of_k,
+                              const double2* __restrict__ Cf, double2* __restrict__ out)
+{
+    const int nc = ncols - 1;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * K;
+    if (idx >= total) return;
+    const int k = (int)(idx % K);
+    const int ob = (int)(idx / K);
+    const int n = row_of_k[k];
+    const int len = nphi[n];
+    const int jp = k - row_off[n];
+    const int band = min(ncols, len) / 2 - 1;
+    const double2* c = Cf + ((int64_t)ob * rows + n) * nc + (ncols / 2 - 1);
+    double re = 0.0, im = 0.0;
+    for (int mu = -band; mu <= band; ++mu) {
+        long t = ((long)mu * jp) % len;
+        if (t < 0) t += len;
+        double sn, cs;
+        sincospi(2.0 * (double)t / len, &sn, &cs);
+        double2 v = c[mu];
+        re += v.x * cs - v.y * sn;
+        im += v.x * sn + v.y * cs;
+    }
+    out[idx] = make_double2(re, im);
+}
+
+template <class R>
+__global__ void to_precision(const double2* __restrict__ in, int64_t n, void* __restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (sizeof(R) == 8) {
+        ((double2*)out)[i] = in[i];
+    } else {
+        ((float2*)out)[i] = make_float2((float)in[i].x, (float)in[i].y);
+    }
+}
+
+// |sin t| Fourier coefficient (Section 3.1.3)
+double sin_abs_coeff(long n)
+{
+    if (n % 2 != 0) return 0.0;
+    double nn = (double)n;
+    return 2.0 / (kPi * (1.0 - nn * nn));
+}
+
+// Real Fourier-resample (Dirichlet) matrix entry: samples j of N points -> sample jp of N' points,
+// keeping |k| <= min(N, N')/2 - 1 (the Nyquist bin dropped):
+//   (1/N) sum_{|k|<=B} e^{i k (2 pi jp / N' - 2 pi j / N)} = sin((2B+1) pi t / NN') / (N sin(pi t / NN'))
+// with t = jp N - j N' reduced modulo N N' (exact integers).
+double dirichlet(int N, int Np, int j, int jp)
+{
+    const int B = std::min(N, Np) / 2 - 1;
+    const long M = (long)N * Np;
+    long t = ((long)jp * N - (long)j * Np) % M;
+    if (t < 0) t += M;
+    if (t == 0) return (2.0 * B + 1.0) / N;
+    long u = ((2L * B + 1L) * t) % (2 * M);
+    double num = std::sin(kPi * (double)u / (double)M);
+    double den = std::sin(kPi * (double)t / (double)M);
+    return num / (N * den);
+}
+
+template <class R>
+void upload_real(DeviceArena& a, void** dst, const std::vector<double>& v, hipStream_t s)
+{
+    std::vector<R> h(v.begin(), v.end());
+    *dst = a.alloc(sizeof(R) * std::max<size_t>(h.size(), 1));
+    FFMM_HIP(hipMemcpyAsync(*dst, h.data(), sizeof(R) * h.size(), hipMemcpyHostToDevice, s));
+    FFMM_HIP(hipStreamSynchronize(s));
+}
+
+template <class R>
+void upload_complex(DeviceArena& a, void** dst, const std::vector<cd>& v, hipStream_t s)
+{
+    std::vector<R> h(2 * v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        h[2 * i] = (R)v[i].real();
+        h[2 * i + 1] = (R)v[i].imag();
+    }
+    *dst = a.alloc(sizeof(R) * std::max<size_t>(h.size(), 1));
+    FFMM_HIP(hipMemcpyAsync(*dst, h.data(), sizeof(R) * h.size(), hipMemcpyHostToDevice, s));
+    FFMM_HIP(hipStreamSynchronize(s));
+}
+
+int32_t* upload_int(DeviceArena& a, const std::vector<int>& v, hipStream_t s)
+{
+    int32_t* d = a.alloc_n<int32_t>(std::max<size_t>(v.size(), 1));
+    FFMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, s));
+    FFMM_HIP(hipStreamSynchronize(s));
+    return d;
+}
+
+// Transfer tables of one level, FP64 on the device, stored in precision R.
+template <class R>
+void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
+{
+    const int ell = L.par.ell, ntheta = L.par.ntheta, rows = L.nrows, K = L.K;
+    const int nt = 2 * ell + 1;
+    const int ncols = 4 * ((2 * ell + 2 + 3) / 4);
+    const int kmax = ntheta / 2 - 1;
+    // B[n][j] = Re sum_{|k|<=kmax} e^{i k theta_n} sum_{|p|<=ell} s_{k-p} e^{-i p theta'_j} / nt
+    std::vector<cd> C((size_t)(2 * kmax + 1) * nt);
+    std::vector<cd> ep(nt * (size_t)(2 * ell + 1));
+    for (int pp = -ell; pp <= ell; ++pp)
+        for (int j = 0; j < nt; ++j) {
+            long t = ((long)pp * j) % nt;
+            ep[(size_t)(pp + ell) * nt + j] = std::exp(cd(0.0, -2.0 * kPi * (double)t / nt));
+        }
+    for (int k = -kmax; k <= kmax; ++k)
+        for (int pp = -ell; pp <= ell; ++pp) {
+            double sk = sin_abs_coeff(k - pp);
+            if (sk == 0.0) continue;
+            cd* crow = &C[(size_t)(k + kmax) * nt];
+            const cd* e = &ep[(size_t)(pp + ell) * nt];
+            for (int j = 0; j < nt; ++j) crow[j] += sk * e[j];
+        }
+    std::vector<double> B((size_t)rows * nt, 0.0);
+    for (int n = 0; n < rows; ++n)
+        for (int k = -kmax; k <= kmax; ++k) {
+            long t = ((long)k * n) % ntheta;
+            cd e = std::exp(cd(0.0, 2.0 * kPi * (double)t / ntheta));
+            const cd* crow = &C[(size_t)(k + kmax) * nt];
+            for (int j = 0; j < nt; ++j) B[(size_t)n * nt + j] += (e * crow[j]).real() / nt;
+        }
+    DeviceArena tmp;
+    try {
+        double* dB = tmp.alloc_n<double>(B.size());
+        FFMM_HIP(hipMemcpy(dB, B.data(), sizeof(double) * B.size(), hipMemcpyHostToDevice));
+        std::vector<int> row_of_k(K);
+        for (int n = 0; n < rows; ++n)
+            for (int k = L.row_off[n]; k < L.row_off[n + 1]; ++k) row_of_k[k] = n;
+        int32_t* d_rok = upload_int(tmp, row_of_k, s);
+        // offsets, coefficient sets per offset
+        int32_t map[kNumCodes];
+        offset_code_map(map);
+        std::vector<double> r0hat(3 * kNumOffsets);
+        std::vector<cd> cn((size_t)kNumOffsets * (ell + 1));
+        std::vector<double> jn(ell + 1), yn(ell + 1);
+        for (int c = 0; c < kNumCodes; ++c) {
+            int o = map[c];
+            if (o < 0) continue;
+            int d[3] = {c % 7 - 3, (c / 7) % 7 - 3, c / 49 - 3};
+            double len = std::sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+            for (int a = 0; a < 3; ++a) r0hat[3 * o + a] = d[a] / len;
+            const double r0 = len * L.a;   // physical |r0|
+            sph_bessel_j(ell, p->kappa * r0, jn.data());
+            sph_bessel_y(ell, p->kappa * r0, yn.data());
+            cd ipow(1.0, 0.0);
+            for (int n = 0; n <= ell; ++n) {
+                // c_n = (i kappa / 4 pi) i^n (2n+1) h_n(kappa |r0|)  (eqn. TransferFn)
+                cn[(size_t)o * (ell + 1) + n] =
+                    cd(0.0, p->kappa / (4.0 * kPi)) * ipow * (2.0 * n + 1.0) * cd(jn[n], yn[n]);
+                ipow *= cd(0.0, 1.0);
+            }
+        }
+        double2* dcn = tmp.alloc_n<double2>(cn.size());
+        FFMM_HIP(hipMemcpy(dcn, cn.data(), sizeof(double2) * cn.size(), hipMemcpyHostToDevice));
+        double* dr0 = tmp.alloc_n<double>(r0hat.size());
+        FFMM_HIP(hipMemcpy(dr0, r0hat.data(), sizeof(double) * r0hat.size(), hipMemcpyHostToDevice));
+        // batch the offsets so that the samples stay below ~256 MB
+        const size_t per_off = sizeof(double2) * ((size_t)nt * ncols + 2 * (size_t)rows * ncols);
+        int batch = (int)std::max<size_t>(1, std::min<size_t>(kNumOffsets, (256u << 20) / per_off));
+        double2* A = tmp.alloc_n<double2>((size_t)batch * nt * ncols);
+        double2* TL = tmp.alloc_n<double2>((size_t)batch * rows * ncols);
+        double2* Cf = tmp.alloc_n<double2>((size_t)batch * rows * (ncols - 1));
+        double2* T64 = tmp.alloc_n<double2>((size_t)kNumOffsets * K);
+        std::vector<cd> tw(ncols);
+        for (int t = 0; t < ncols; ++t) tw[t] = std::exp(cd(0.0, -2.0 * kPi * t / ncols));
+        double2* dtw = tmp.alloc_n<double2>(ncols);
+        FFMM_HIP(hipMemcpy(dtw, tw.data(), sizeof(double2) * ncols, hipMemcpyHostToDevice));
+        for (int o0 = 0; o0 < kNumOffsets; o0 += batch) {
+            const int nb = std::min(batch, kNumOffsets - o0);
+            int64_t tot = (int64_t)nb * nt * ncols;
+            hipLaunchKernelGGL(bmtf_sample, dim3(nblk(tot, 256)), dim3(256), 0, s, nb, ell, ncols,
+                               dcn + (size_t)o0 * (ell + 1), dr0 + 3 * o0, A);
+            FFMM_LAUNCH_CHECK();
+            tot = (int64_t)nb * rows * ncols;
+            hipLaunchKernelGGL(bmtf_theta, dim3(nblk(tot, 256)), dim3(256), 0, s, nb, nt, rows, ncols,
+                               dB, A, TL);
+            FFMM_LAUNCH_CHECK();
+            tot = (int64_t)nb * rows * (ncols - 1);
+            hipLaunchKernelGGL(bmtf_phi_coef, dim3(nblk(tot, 256)), dim3(256), 0, s, nb, rows, ncols,
+                               dtw, TL, Cf);
+            FFMM_LAUNCH_CHECK();
+            tot = (int64_t)nb * K;
+            hipLaunchKernelGGL(bmtf_phi_eval, dim3(nblk(tot, 256)), dim3(256), 0, s, nb, rows, ncols, K,
+                               L.d_row_off, L.d_nphi, d_rok, Cf, T64 + (size_t)o0 * K);
+            FFMM_LAUNCH_CHECK();
+        }
+        const int64_t tot = (int64_t)kNumOffsets * K;
+        L.transfer = p->arena.alloc(sizeof(R) * 2 * tot);
+        hipLaunchKernelGGL(to_precision<R>, dim3(nblk(tot, 256)), dim3(256), 0, s, T64, tot, L.transfer);
+        FFMM_LAUNCH_CHECK();
+        FFMM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        tmp.release();
+        throw;
+    }
+    tmp.release();
+}
+
+template <class R>
+void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resampler& rs, hipStream_t s)
+{
+    int na = 0;
+    for (int v : S.par.nphi) na = std::max(na, v);
+    for (int v : D.par.nphi) na = std::max(na, v);
+    rs.nphi_all = na;
+    rs.nt_src = S.par.ntheta;
+    rs.nt_dst = D.par.ntheta;
+    rs.rows_src = S.nrows;
+    rs.rows_dst = D.nrows;
+    rs.K_src = S.K;
+    rs.K_dst = D.K;
+    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * rs.nt_dst), d5((size_t)D.K * na);
+    for (int n = 0; n < S.nrows; ++n) {
+        const int len = S.par.nphi[n];
+        double* blk = &d1[(size_t)S.row_off[n] * na];
+        for (int m = 0; m < len; ++m)
+            for (int j = 0; j < na; ++j) blk[(size_t)m * na + j] = dirichlet(len, na, m, j);
+    }
+    for (int t = 0; t < rs.nt_src; ++t)
+        for (int tp = 0; tp < rs.nt_dst; ++tp)
+            dth[(size_t)t * rs.nt_dst + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
+    for (int n = 0; n < D.nrows; ++n) {
+        const int len = D.par.nphi[n];
+        double* blk = &d5[(size_t)D.row_off[n] * na];
+        for (int j = 0; j < na; ++j)
+            for (int jp = 0; jp < len; ++jp) blk[(size_t)j * len + jp] = dirichlet(na, len, j, jp);
+    }
+    upload_real<R>(p->arena, &rs.d1, d1, s);
+    upload_real<R>(p->arena, &rs.dth, dth, s);
+    upload_real<R>(p->arena, &rs.d5, d5, s);
+    rs.d_src_row_off = S.d_row_off;
+    rs.d_src_nphi = S.d_nphi;
+    rs.d_dst_row_off = D.d_row_off;
+    rs.d_dst_nphi = D.d_nphi;
+    std::vector<int> rok(D.K);
+    for (int n = 0; n < D.nrows; ++n)
+        for (int k = D.row_off[n]; k < D.row_off[n + 1]; ++k) rok[k] = n;
+    rs.d_dst_row_of_k = upload_int(p->arena, rok, s);
+}
+
+template <class R>
+void build_tables_t(ffmm_plan* p, hipStream_t s)
+{
+    const int depth = p->depth;
+    const double u = p->prec == FFMM_FP32 ? kUnitRoundoffFP32 : kUnitRoundoffFP64;
+    p->predicted.assign(depth + 1, 0.0);
+    for (int l = 2; l <= depth; ++l) {
+        LevelData& L = p->lev[l];
+        const double ka = p->kappa * L.a;
+        const int ell_in = (l < FFMM_MAX_LEVELS) ? p->opt.ell_override[l] : 0;
+        level_params(ka, p->opt.alpha, p->opt.eps_safety * p->eps, u, ell_in, &L.par);
+        p->predicted[l] = L.par.predicted;
+        L.nrows = L.par.ntheta / 2 + 1;
+        L.row_off.assign(L.nrows + 1, 0);
+        for (int n = 0; n < L.nrows; ++n) L.row_off[n + 1] = L.row_off[n] + L.par.nphi[n];
+        L.K = L.row_off[L.nrows];
+        L.d_row_off = upload_int(p->arena, L.row_off, s);
+        L.d_nphi = upload_int(p->arena, L.par.nphi, s);
+        // directions (and leaf weights)
+        std::vector<double> dirs(3 * (size_t)L.K), w(L.K);
+        for (int n = 0; n < L.nrows; ++n) {
+            const double th = 2.0 * kPi * n / L.par.ntheta;
+            const int len = L.par.nphi[n];
+            const double wn = 4.0 * kPi * kPi / ((double)L.par.ntheta * len) *
+                              ((n == 0 || n == L.nrows - 1) ? 1.0 : 2.0);
+            for (int m = 0; m < len; ++m) {
+                const double ph = 2.0 * kPi * m / len;
+                const int k = L.row_off[n] + m;
+                dirs[3 * k] = std::cos(ph) * std::sin(th);
+                dirs[3 * k + 1] = std::sin(ph) * std::sin(th);
+                dirs[3 * k + 2] = std::cos(th);
+                w[k] = wn;
+            }
+        }
+        upload_real<R>(p->arena, &L.dirs, dirs, s);
+        if (l == depth) upload_real<R>(p->arena, &L.weights, w, s);
+        transfer_tables<R>(p, L, s);
+        if (l < depth) {
+            // e^{i kappa s.(oct - 1/2) a_{l+1}}, oct = (x, y, z) bits of the child position
+            const double ac = p->lev[l + 1].a;
+            std::vector<cd> tr(8 * (size_t)L.K);
+            for (int o = 0; o < 8; ++o) {
+                const double d[3] = {((o & 1) - 0.5) * ac, (((o >> 1) & 1) - 0.5) * ac,
+                                     (((o >> 2) & 1) - 0.5) * ac};
+                for (int k = 0; k < L.K; ++k) {
+                    const double ph = p->kappa * (dirs[3 * k] * d[0] + dirs[3 * k + 1] * d[1] +
+                                                  dirs[3 * k + 2] * d[2]);
+                    tr[(size_t)o * L.K + k] = cd(std::cos(ph), std::sin(ph));
+                }
+            }
+            upload_complex<R>(p->arena, &L.trans, tr, s);
+        }
+    }
+    p->up.assign(depth + 1, Resampler{});
+    p->down.assign(depth + 1, Resampler{});
+    for (int l = 3; l <= depth; ++l) make_resampler<R>(p, p->lev[l], p->lev[l - 1], p->up[l], s);
+    for (int l = 2; l < depth; ++l) make_resampler<R>(p, p->lev[l], p->lev[l + 1], p->down[l], s);
+}
+
+}  // namespace
+
+void build_tables(ffmm_plan* p, hipStream_t s)
+{
+    if (p->prec == FFMM_FP32)
+        build_tables_t<float>(p, s);
+    else
+        build_tables_t<double>(p, s);
+}
+
+}  // namespace ffmm

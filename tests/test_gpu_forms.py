@@ -1,0 +1,94 @@
+"""Adjoint, field gradient, batched right-hand sides and autograd of the HIP path against the
+oracle's direct sums (C-ABI calls through the binding)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_0911_4114_amd as ff
+from paper_0911_4114_amd import workloads as wl
+from oracle import direct
+from _gpu_common import log, dev_points, dev_complex, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+N = 12000
+KAPPA = 45.0
+
+
+@pytest.fixture(scope="module")
+def setup():
+    assert torch.cuda.is_available()
+    x = wl.sphere_points(N, seed=4)
+    return x, dev_points(x)
+
+
+@pytest.mark.parametrize("prec,eps", [("fp64", 1e-6), ("fp32", 1e-4)])
+def test_adjoint_is_conj_a_conj(setup, prec, eps):
+    x, xt = setup
+    g = wl.complex_normal(N, seed=5)
+    p = ff.Plan(xt, KAPPA, eps, precision=prec)
+    out = p.adjoint(dev_complex(g, prec == "fp32")).cpu().numpy().astype(complex)
+    ref = np.conj(direct.matvec(x, np.conj(g), KAPPA))
+    log("adjoint %s err %.3e" % (prec, rel_l2(out, ref)))
+    assert rel_l2(out, ref) < eps
+    # dot-product test <A q, g> = <q, A^H g> up to the approximation error
+    q = wl.complex_normal(N, seed=6)
+    aq = p.matvec(dev_complex(q, prec == "fp32")).cpu().numpy().astype(complex)
+    lhs = np.vdot(g, aq)
+    rhs = np.vdot(out, q)
+    assert abs(lhs - rhs) <= 10 * eps * np.linalg.norm(aq) * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("prec,eps,tol", [("fp64", 1e-6, 1e-5), ("fp32", 1e-4, 1e-3)])
+def test_field_gradient(setup, prec, eps, tol):
+    x, xt = setup
+    q = wl.complex_normal(N, seed=7)
+    p = ff.Plan(xt, KAPPA, eps, precision=prec)
+    out = p.field_gradient(dev_complex(q, prec == "fp32")).cpu().numpy().astype(complex)
+    tg = wl.subset(N, 2000)
+    ref = direct.gradient(x, q, KAPPA, targets=tg)
+    err = rel_l2(out[tg], ref)
+    log("gradient %s err %.3e" % (prec, err))
+    assert err < tol
+
+
+def test_batched_rhs_equal_single(setup):
+    x, xt = setup
+    Q = wl.plane_wave_charges(x, KAPPA, 4, seed=2)
+    p = ff.Plan(xt, KAPPA, 1e-4, precision="fp32", max_rhs=4)
+    out = p.matvec(dev_complex(Q, True)).cpu().numpy()
+    for m in range(4):
+        one = p.matvec(dev_complex(Q[m], True)).cpu().numpy()
+        assert np.array_equal(out[m], one)
+    tg = wl.subset(N, 500)
+    ref = direct.matvec(x, Q[1], KAPPA, targets=tg)
+    assert rel_l2(out[1][tg], ref) < 1e-4
+    with pytest.raises(ff.FfmmError):
+        p.matvec(dev_complex(np.ones((5, N)), True))
+
+
+def test_autograd_matches_oracle_gradients(setup):
+    x, xt = setup
+    n = 3000
+    x = x[:n]
+    xt = dev_points(x)
+    kappa = 30.0
+    q = wl.complex_normal(n, seed=8)
+    phit = wl.complex_normal(n, seed=9)
+    p = ff.Plan(xt, kappa, 1e-6, precision="fp64", max_rhs=2)
+    xq = xt.clone().requires_grad_(True)
+    qq = dev_complex(q).requires_grad_(True)
+    phi = ff.apply(p, xq, qq)
+    loss = (phi - dev_complex(phit)).abs().pow(2).sum()
+    loss.backward()
+    # oracle: G = 2 (phi - phi_t); dL/dq = conj(A conj G); dL/dx_i = Re[conj(G_i) F_i(q) + q_i F_i(conj G)]
+    phi_ref = direct.matvec(x, q, kappa)
+    G = 2.0 * (phi_ref - phit)
+    gq = np.conj(direct.matvec(x, np.conj(G), kappa))
+    Fq = direct.gradient(x, q, kappa)
+    FG = direct.gradient(x, np.conj(G), kappa)
+    gx = np.real(np.conj(G)[:, None] * Fq + q[:, None] * FG)
+    eq = rel_l2(qq.grad.cpu().numpy(), gq)
+    ex = rel_l2(xq.grad.cpu().numpy(), gx)
+    log("autograd errs q %.3e x %.3e" % (eq, ex))
+    assert eq < 1e-5 and ex < 1e-4
