@@ -88,6 +88,10 @@ struct Resampler {
     int32_t* d_dst_row_off = nullptr;
     int32_t* d_dst_nphi = nullptr;
     int32_t* d_dst_row_of_k = nullptr; // [K_dst] row of each destination sample
+    // upward pass: child tiles made of whole parents (at most 32 children each)
+    int ntiles = 0;
+    int32_t* tile_begin = nullptr;
+    int32_t* tile_end = nullptr;
 };
 
 }  // namespace ffmm
@@ -149,6 +153,11 @@ struct StageScope {
     StageScope(ffmm_plan* plan, int st, hipStream_t stream);
     ~StageScope() noexcept(false);
 };
+
+// five-step resample between adjacent levels: M2M when l_dst = l_src - 1, L2L when l_src + 1
+void run_resample(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s);
+void make_parent_tiles(const std::vector<int32_t>& child_count, std::vector<int32_t>& begin,
+                       std::vector<int32_t>& end);
 
 // map offset code (0..342) -> transfer table row (0..315), -1 for the inner 27 codes
 void offset_code_map(int32_t* map);

@@ -149,148 +149,6 @@ __global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* _
 }
 
 // ------------------------------------------------------------------------------------------
-// Five-step inter/anterpolation between level quadratures (Section 3.4), each 1D step a real
-// Fourier-resample matrix (the Dirichlet kernel with the Nyquist bin dropped).
-// step 1: G1[c][n][j] = sum_m D1_n[m][j] in_c(row n, m), j < NA.
-//   UP:   in_c = M^l_c (child signature, level-l grid).
-//   DOWN: in_c = L^l_{parent(c)} * conj(E_oct(c)) (translation applied on the parent grid).
-// ------------------------------------------------------------------------------------------
-template <class R, class C, bool DOWN>
-__global__ __launch_bounds__(256) void rs_step1(int64_t nb, int rows, int NA,
-                                                const int32_t* __restrict__ row_off,
-                                                const int32_t* __restrict__ nphi,
-                                                const R* __restrict__ d1, const C* __restrict__ sig,
-                                                int Ksrc, int64_t nb_in,
-                                                const int32_t* __restrict__ parent,
-                                                const int32_t* __restrict__ octant,
-                                                const C* __restrict__ trans, C* __restrict__ G1)
-{
-    const int64_t total = nb * rows * NA;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t r = blockIdx.y;
-    const int j = (int)(idx % NA);
-    const int nrow = (int)((idx / NA) % rows);
-    const int64_t c = idx / ((int64_t)NA * rows);
-    const int len = nphi[nrow], off = row_off[nrow];
-    const R* D = d1 + (int64_t)off * NA + j;
-    const int64_t cin = DOWN ? parent[c] : c;
-    const C* in = sig + (r * nb_in + cin) * Ksrc + off;
-    const C* tr = DOWN ? trans + (int64_t)octant[c] * Ksrc + off : nullptr;
-    C acc = cz<C>();
-    for (int m = 0; m < len; ++m) {
-        C v = in[m];
-        if (DOWN) v = cmulconj(v, tr[m]);
-        const R d = D[(int64_t)m * NA];
-        acc.x += d * v.x;
-        acc.y += d * v.y;
-    }
-    G1[((r * nb + c) * rows + nrow) * NA + j] = acc;
-}
-
-// step 2 + 3: theta-periodic sequence of column m (< NA/2) built with the symmetry
-// F(theta_t, phi_m) = F(theta_{ntS - t}, phi_{m + NA/2}) (eqn. NumSphereSym) and resampled from
-// ntS to ntD points. G2[c][m][t'].
-template <class R, class C>
-__global__ __launch_bounds__(256) void rs_step3(int64_t nb, int NA, int rowsS, int ntS, int ntD,
-                                                const R* __restrict__ dth,
-                                                const C* __restrict__ G1, C* __restrict__ G2)
-{
-    const int half = NA / 2;
-    const int64_t total = nb * half * ntD;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t r = blockIdx.y;
-    const int tp = (int)(idx % ntD);
-    const int m = (int)((idx / ntD) % half);
-    const int64_t c = idx / ((int64_t)ntD * half);
-    const C* g = G1 + (r * nb + c) * rowsS * NA;
-    C acc = cz<C>();
-    for (int t = 0; t < ntS; ++t) {
-        C v = (t <= ntS / 2) ? g[t * NA + m] : g[(ntS - t) * NA + m + half];
-        const R d = dth[(int64_t)t * ntD + tp];
-        acc.x += d * v.x;
-        acc.y += d * v.y;
-    }
-    G2[((r * nb + c) * half + m) * ntD + tp] = acc;
-}
-
-// steps 4 + 5 for one box: destination row n' rebuilt over NA columns by the same symmetry, then
-// resampled to N'_phi(theta'_n'); returns the value at destination sample k.
-template <class R, class C>
-__device__ inline C rs_row_value(const C* __restrict__ g2, int NA, int ntD, int nrow, int jp,
-                                 int len, const R* __restrict__ d5blk)
-{
-    const int half = NA / 2;
-    const int tneg = (ntD - nrow) % ntD;
-    C acc = cz<C>();
-    for (int j = 0; j < NA; ++j) {
-        C v = (j < half) ? g2[(int64_t)j * ntD + nrow] : g2[(int64_t)(j - half) * ntD + tneg];
-        const R d = d5blk[(int64_t)j * len + jp];
-        acc.x += d * v.x;
-        acc.y += d * v.y;
-    }
-    return acc;
-}
-
-// UP (M2M, Section 2): M^{l-1}_p(s_k) = sum_{c child of p} E_oct(c)(s_k) R(M^l_c)(s_k).
-template <class R, class C>
-__global__ __launch_bounds__(256) void rs_step5_up(int64_t np, int Kd, int NA, int ntD,
-                                                   const int32_t* __restrict__ row_of_k,
-                                                   const int32_t* __restrict__ row_off,
-                                                   const int32_t* __restrict__ nphi,
-                                                   const R* __restrict__ d5, const C* __restrict__ G2,
-                                                   int64_t nb_child,
-                                                   const int32_t* __restrict__ child_start,
-                                                   const int32_t* __restrict__ child_count,
-                                                   const int32_t* __restrict__ octant,
-                                                   const C* __restrict__ trans, C* __restrict__ out)
-{
-    const int64_t total = np * Kd;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t r = blockIdx.y;
-    const int k = (int)(idx % Kd);
-    const int64_t p = idx / Kd;
-    const int nrow = row_of_k[k];
-    const int off = row_off[nrow], len = nphi[nrow];
-    const R* blk = d5 + (int64_t)off * NA;
-    const int half = NA / 2;
-    C acc = cz<C>();
-    const int c0 = child_start[p], cn = child_count[p];
-    for (int c = c0; c < c0 + cn; ++c) {
-        const C* g2 = G2 + (r * nb_child + c) * half * ntD;
-        C v = rs_row_value<R, C>(g2, NA, ntD, nrow, k - off, len, blk);
-        cmac(acc, v, trans[(int64_t)octant[c] * Kd + k]);
-    }
-    out[(r * np + p) * Kd + k] = acc;
-}
-
-// DOWN (L2L, Section 2): L^{l+1}_c += R(L^l_p conj(E_oct(c))) (L^{l+1}_c already holds I^{l+1}_c).
-template <class R, class C>
-__global__ __launch_bounds__(256) void rs_step5_down(int64_t nc, int Kd, int NA, int ntD,
-                                                     const int32_t* __restrict__ row_of_k,
-                                                     const int32_t* __restrict__ row_off,
-                                                     const int32_t* __restrict__ nphi,
-                                                     const R* __restrict__ d5,
-                                                     const C* __restrict__ G2, C* __restrict__ out)
-{
-    const int64_t total = nc * Kd;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t r = blockIdx.y;
-    const int k = (int)(idx % Kd);
-    const int64_t c = idx / Kd;
-    const int nrow = row_of_k[k];
-    const int off = row_off[nrow], len = nphi[nrow];
-    const C* g2 = G2 + (r * nc + c) * (NA / 2) * ntD;
-    C v = rs_row_value<R, C>(g2, NA, ntD, nrow, k - off, len, d5 + (int64_t)off * NA);
-    C& o = out[(r * nc + c) * Kd + k];
-    o.x += v.x;
-    o.y += v.y;
-}
-
-// ------------------------------------------------------------------------------------------
 // M2L (Transfer pass, Section 2): I_b(s_k) = sum_{e in I(b)} M_src(e)(s_k) T_off(e)(s_k).
 // Block: one target box, 256 directions; the interaction list is staged in LDS.
 // ------------------------------------------------------------------------------------------
@@ -530,31 +388,10 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n);
             FFMM_LAUNCH_CHECK();
         }
-        // M2M, l = L..3
+        // M2M, l = L..3 (five-step resample to the parent grid, translate, sum children)
         for (int l = L; l >= 3; --l) {
             StageScope sc(p, FFMM_PROF_M2M, s);
-            LevelData& Cl = p->lev[l];
-            LevelData& P = p->lev[l - 1];
-            Resampler& rs = p->up[l];
-            C* G1 = (C*)p->scratch1;
-            C* G2 = (C*)p->scratch2;
-            int64_t tot = Cl.n * rs.rows_src * rs.nphi_all;
-            hipLaunchKernelGGL((rs_step1<R, C, false>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s,
-                               Cl.n, rs.rows_src, rs.nphi_all, rs.d_src_row_off, rs.d_src_nphi,
-                               (const R*)rs.d1, (const C*)Cl.sigM, Cl.K, Cl.n, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr, (const C*)nullptr, G1);
-            FFMM_LAUNCH_CHECK();
-            tot = Cl.n * (rs.nphi_all / 2) * rs.nt_dst;
-            hipLaunchKernelGGL((rs_step3<R, C>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s, Cl.n,
-                               rs.nphi_all, rs.rows_src, rs.nt_src, rs.nt_dst, (const R*)rs.dth,
-                               (const C*)G1, G2);
-            FFMM_LAUNCH_CHECK();
-            tot = P.n * P.K;
-            hipLaunchKernelGGL((rs_step5_up<R, C>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s, P.n,
-                               P.K, rs.nphi_all, rs.nt_dst, rs.d_dst_row_of_k, rs.d_dst_row_off,
-                               rs.d_dst_nphi, (const R*)rs.d5, (const C*)G2, Cl.n, P.child_start,
-                               P.child_count, Cl.octant, (const C*)P.trans, (C*)P.sigM);
-            FFMM_LAUNCH_CHECK();
+            run_resample(p, l, l - 1, nrhs, s);
         }
         // M2L, l = 2..L (written into the L buffers, which then receive the downward pass)
         for (int l = 2; l <= L; ++l) {
@@ -566,30 +403,10 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n);
             FFMM_LAUNCH_CHECK();
         }
-        // L2L, l = 2..L-1
+        // L2L, l = 2..L-1 (translate on the parent grid, five-step resample, add to I)
         for (int l = 2; l < L; ++l) {
             StageScope sc(p, FFMM_PROF_L2L, s);
-            LevelData& P = p->lev[l];
-            LevelData& Cl = p->lev[l + 1];
-            Resampler& rs = p->down[l];
-            C* G1 = (C*)p->scratch1;
-            C* G2 = (C*)p->scratch2;
-            int64_t tot = Cl.n * rs.rows_src * rs.nphi_all;
-            hipLaunchKernelGGL((rs_step1<R, C, true>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s,
-                               Cl.n, rs.rows_src, rs.nphi_all, rs.d_src_row_off, rs.d_src_nphi,
-                               (const R*)rs.d1, (const C*)P.sigL, P.K, P.n, Cl.parent, Cl.octant,
-                               (const C*)P.trans, G1);
-            FFMM_LAUNCH_CHECK();
-            tot = Cl.n * (rs.nphi_all / 2) * rs.nt_dst;
-            hipLaunchKernelGGL((rs_step3<R, C>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s, Cl.n,
-                               rs.nphi_all, rs.rows_src, rs.nt_src, rs.nt_dst, (const R*)rs.dth,
-                               (const C*)G1, G2);
-            FFMM_LAUNCH_CHECK();
-            tot = Cl.n * Cl.K;
-            hipLaunchKernelGGL((rs_step5_down<R, C>), dim3(nblk(tot, 256), nrhs), dim3(256), 0, s, Cl.n,
-                               Cl.K, rs.nphi_all, rs.nt_dst, rs.d_dst_row_of_k, rs.d_dst_row_off,
-                               rs.d_dst_nphi, (const R*)rs.d5, (const C*)G2, (C*)Cl.sigL);
-            FFMM_LAUNCH_CHECK();
+            run_resample(p, l, l + 1, nrhs, s);
         }
         // L2P
         StageScope sc(p, FFMM_PROF_L2P, s);

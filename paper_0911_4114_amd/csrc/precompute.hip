@@ -354,6 +354,14 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     for (int n = 0; n < D.nrows; ++n)
         for (int k = D.row_off[n]; k < D.row_off[n + 1]; ++k) rok[k] = n;
     rs.d_dst_row_of_k = upload_int(p->arena, rok, s);
+    if (D.l == S.l - 1) {
+        std::vector<int32_t> cc(D.n), tb, te;
+        FFMM_HIP(hipMemcpy(cc.data(), D.child_count, sizeof(int32_t) * D.n, hipMemcpyDeviceToHost));
+        make_parent_tiles(cc, tb, te);
+        rs.ntiles = (int)tb.size();
+        rs.tile_begin = upload_int(p->arena, std::vector<int>(tb.begin(), tb.end()), s);
+        rs.tile_end = upload_int(p->arena, std::vector<int>(te.begin(), te.end()), s);
+    }
 }
 
 template <class R>
