@@ -181,69 +181,80 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
 // ------------------------------------------------------------------------------------------
 // L2P (far part of eqn. FMM_FinalStep): phi_i += sum_k w_k L_b(s_k) e^{i kappa s_k.(c_b - x_i)};
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
-// One wave per target point, lanes split k; the partial sums are carried with TwoSum so that the
-// FP32 sum of large cancelling terms keeps its accumulation error at the size of the result.
+// One wave per leaf box, one lane per target point; w_k L_b(s_k) and s_k are staged in LDS in
+// chunks. The sum over k is blocked: plain sums of 16 terms, combined with TwoSum, which keeps
+// the FP32 accumulation error of the large cancelling terms near the size of the result.
 // ------------------------------------------------------------------------------------------
+constexpr int kL2PChunk = 512;
+
 template <class R, class C, bool GRAD>
-__global__ __launch_bounds__(256) void l2p_kernel(int K, const R* __restrict__ dirs,
-                                                  const R* __restrict__ w, R kfac, R kappa,
-                                                  const int32_t* __restrict__ start,
-                                                  const int32_t* __restrict__ count,
-                                                  const R* __restrict__ rel, const C* __restrict__ L,
-                                                  C* __restrict__ out, int64_t n, int64_t nb)
+__global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__ dirs,
+                                                    const R* __restrict__ w, R kfac, R kappa,
+                                                    const int32_t* __restrict__ start,
+                                                    const int32_t* __restrict__ count,
+                                                    const R* __restrict__ rel, const C* __restrict__ L,
+                                                    C* __restrict__ out, int64_t n, int64_t nb)
 {
     constexpr int NC = GRAD ? 3 : 1;
+    __shared__ R sx[kL2PChunk], sy[kL2PChunk], sz[kL2PChunk];
+    __shared__ C swl[kL2PChunk];
     const int64_t b = blockIdx.x;
     const int64_t r = blockIdx.y;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int lane = threadIdx.x;
     const int s0 = start[b], cnt = count[b];
     const C* Lb = L + (r * nb + b) * K;
-    for (int pt = wave; pt < cnt; pt += 4) {
-        const int64_t i = s0 + pt;
-        const R x = -rel[3 * i], y = -rel[3 * i + 1], z = -rel[3 * i + 2];  // c_b - x_i
+    for (int t0 = 0; t0 < cnt; t0 += kWave) {
+        const bool valid = t0 + lane < cnt;
+        const int64_t i = s0 + t0 + lane;
+        R x = 0, y = 0, z = 0;
+        if (valid) {
+            x = -rel[3 * i] * kfac;      // kappa (c_b - x_i), in the phase units of R
+            y = -rel[3 * i + 1] * kfac;
+            z = -rel[3 * i + 2] * kfac;
+        }
         R sre[NC], sim[NC], ere[NC], eim[NC];
         for (int a = 0; a < NC; ++a) sre[a] = sim[a] = ere[a] = eim[a] = 0;
-        for (int k = lane; k < K; k += kWave) {
-            const R sx = dirs[3 * k], sy = dirs[3 * k + 1], sz = dirs[3 * k + 2];
-            R c, s;
-            cis(kfac * (sx * x + sy * y + sz * z), c, s);
-            C lv = Lb[k];
-            const R wk = w[k];
-            C t = cmul(cmk<C>(c, s), cmk<C>(wk * lv.x, wk * lv.y));
-            if (GRAD) {
-                // (-i kappa s_a) t
-                const R sa[3] = {sx, sy, sz};
-                for (int a = 0; a < 3; ++a) {
-                    R tr = kappa * sa[a] * t.y, ti = -kappa * sa[a] * t.x;
+        for (int k0 = 0; k0 < K; k0 += kL2PChunk) {
+            const int nk = min(kL2PChunk, K - k0);
+            __syncthreads();
+            for (int k = lane; k < nk; k += kWave) {
+                const int kk = k0 + k;
+                sx[k] = dirs[3 * kk];
+                sy[k] = dirs[3 * kk + 1];
+                sz[k] = dirs[3 * kk + 2];
+                const C lv = Lb[kk];
+                swl[k] = cmk<C>(w[kk] * lv.x, w[kk] * lv.y);
+            }
+            __syncthreads();
+            for (int kb = 0; kb < nk; kb += 16) {
+                const int ke = min(kb + 16, nk);
+                R pre[NC], pim[NC];
+                for (int a = 0; a < NC; ++a) pre[a] = pim[a] = 0;
+                for (int k = kb; k < ke; ++k) {
+                    R c, s;
+                    cis(sx[k] * x + sy[k] * y + sz[k] * z, c, s);
+                    const C t = cmul(cmk<C>(c, s), swl[k]);
+                    if (GRAD) {
+                        const R sa[3] = {sx[k], sy[k], sz[k]};
+                        for (int a = 0; a < 3; ++a) {       // (-i kappa s_a) t
+                            pre[a] += kappa * sa[a] * t.y;
+                            pim[a] -= kappa * sa[a] * t.x;
+                        }
+                    } else {
+                        pre[0] += t.x;
+                        pim[0] += t.y;
+                    }
+                }
+                for (int a = 0; a < NC; ++a) {
                     R e1, e2;
-                    two_sum(sre[a], tr, sre[a], e1);
-                    two_sum(sim[a], ti, sim[a], e2);
+                    two_sum(sre[a], pre[a], sre[a], e1);
+                    two_sum(sim[a], pim[a], sim[a], e2);
                     ere[a] += e1;
                     eim[a] += e2;
                 }
-            } else {
-                R e1, e2;
-                two_sum(sre[0], t.x, sre[0], e1);
-                two_sum(sim[0], t.y, sim[0], e2);
-                ere[0] += e1;
-                eim[0] += e2;
             }
         }
-        for (int a = 0; a < NC; ++a) {
-            for (int d = kWave / 2; d > 0; d >>= 1) {
-                R os = shfl_down(sre[a], d), oe = shfl_down(ere[a], d);
-                R s1, e1;
-                two_sum(sre[a], os, s1, e1);
-                sre[a] = s1;
-                ere[a] += oe + e1;
-                os = shfl_down(sim[a], d);
-                oe = shfl_down(eim[a], d);
-                two_sum(sim[a], os, s1, e1);
-                sim[a] = s1;
-                eim[a] += oe + e1;
-            }
-        }
-        if (lane == 0)
+        if (valid)
             for (int a = 0; a < NC; ++a) {
                 C& o = out[(r * n + i) * NC + a];
                 o.x += sre[a] + ere[a];
@@ -275,7 +286,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x;
     const int tb = start[b], tc = count[b];
-    const double inv2pi = 1.0 / kTwoPi;
+    const double kappa_rev = kappa / kTwoPi;
     for (int t0 = 0; t0 < tc; t0 += kWave) {
         const bool valid = t0 + lane < tc;
         const int64_t i = tb + t0 + lane;
@@ -306,17 +317,27 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
                     const int64_t j = sb + s0 + t;
                     const double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (j == i || r2 == 0.0) continue;
-                    const double rr = sqrt(r2);
+                    const bool ok = (j != i) && (r2 > 0.0);
                     R c, s, inv;
+                    double rr;
                     if constexpr (sizeof(R) == 4) {
-                        double rev = kappa * rr * inv2pi;
+                        // 1/R from the hardware reciprocal square root of the FP32-rounded R^2,
+                        // refined by one Newton step in FP64 (relative error ~1e-14), so R and the
+                        // phase kappa R / 2 pi stay FP64-accurate; the phase is reduced modulo 1
+                        // in FP64 before the FP32 sine/cosine.
+                        const double r2s = ok ? r2 : 1.0;
+                        const double y0 = (double)__builtin_amdgcn_rsqf((float)r2s);
+                        const double y1 = y0 * (1.5 - 0.5 * r2s * y0 * y0);
+                        rr = r2s * y1;
+                        double rev = rr * kappa_rev;
                         rev -= floor(rev);
                         cis((float)rev, c, s);
-                        inv = 1.0f / (float)rr;
+                        inv = ok ? (float)y1 : 0.0f;
                     } else {
+                        const double r2s = ok ? r2 : 1.0;
+                        rr = sqrt(r2s);
                         cis(kappa * rr, c, s);
-                        inv = 1.0 / rr;
+                        inv = ok ? 1.0 / rr : 0.0;
                     }
                     if (GRAD) {
                         // e^{i kR}(i kR - 1)/R^3 (x_i - x_j)
@@ -411,12 +432,12 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         // L2P
         StageScope sc(p, FFMM_PROF_L2P, s);
         if (gradient)
-            hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3((unsigned)leaf.n, nrhs), dim3(256), 0, s,
+            hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3((unsigned)leaf.n, nrhs), dim3(kWave), 0, s,
                                leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
                                p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
                                phis, n, leaf.n);
         else
-            hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3((unsigned)leaf.n, nrhs), dim3(256), 0, s,
+            hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3((unsigned)leaf.n, nrhs), dim3(kWave), 0, s,
                                leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
                                p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
                                phis, n, leaf.n);
