@@ -138,6 +138,8 @@ __global__ __launch_bounds__(NT) void rs3_gemm(int64_t nb, int NA, int rowsS, in
     const int64_t r = blockIdx.z;
     const int64_t ncols = nb * half;
     const int64_t g0 = (int64_t)blockIdx.x * BC;
+    const int64_t cbase = g0 / half;                 // first (box, column) of the tile
+    const int m0 = (int)(g0 - cbase * half);
     const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
     R acc[4][4] = {};
     for (int k0 = 0; k0 < ntS; k0 += BK) {
@@ -149,13 +151,16 @@ __global__ __launch_bounds__(NT) void rs3_gemm(int64_t nb, int NA, int rowsS, in
         for (int e = tid; e < BK * BC; e += NT) {
             const int cc = e % BC, kk = e / BC;
             const int t = k0 + kk;
-            const int64_t g = g0 + cc;
             C v;
             v.x = 0;
             v.y = 0;
-            if (t < ntS && g < ncols) {
-                const int64_t c = g / half;
-                const int m = (int)(g % half);
+            if (t < ntS && g0 + cc < ncols) {
+                int m = m0 + cc;
+                int64_t c = cbase;
+                while (m >= half) {   // at most BC / half + 1 steps
+                    m -= half;
+                    ++c;
+                }
                 const C* base = G1 + (r * nb + c) * rowsS * NA;
                 v = (t <= ntS / 2) ? base[(int64_t)t * NA + m] : base[(int64_t)(ntS - t) * NA + m + half];
             }
@@ -173,8 +178,12 @@ __global__ __launch_bounds__(NT) void rs3_gemm(int64_t nb, int NA, int rowsS, in
         for (int h = 0; h < 2; ++h) {
             const int64_t g = g0 + tc * 2 + h;
             if (g >= ncols) continue;
-            const int64_t c = g / half;
-            const int m = (int)(g % half);
+            int m = m0 + tc * 2 + h;
+            int64_t c = cbase;
+            while (m >= half) {
+                m -= half;
+                ++c;
+            }
             C v;
             v.x = acc[i][2 * h];
             v.y = acc[i][2 * h + 1];
