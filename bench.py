@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--depth", type=int, default=0,
                     help="leaf level (0: the plan's own choice from max_leaf and eps)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--large", action="store_true",
+                    help="also run 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS")
     ap.add_argument("--no-cpu", action="store_true")
     return ap.parse_args()
 
@@ -165,6 +168,49 @@ def main():
                          % (len(tg), n, n, cpu_s)}
         log("fp32 rel err %.3e; cpu %.4f Mpoints/s" % (rel_err, cpu["value"]))
 
+    batched = None
+    if not args.no_batched:
+        # 16 incident plane waves q_j^(m) = e^{i kappa d_m . x_j} through one tree
+        nb_rhs = 16
+        qb = torch.as_tensor(wl.plane_wave_charges(x, args.kappa, nb_rhs, seed=2),
+                             dtype=torch.complex128, device=dev).to(torch.complex64)
+        pb = ff.Plan(xt, args.kappa, args.eps, precision="fp32", max_rhs=nb_rhs,
+                     depth=args.depth or None)
+        msb = timed(lambda: pb.matvec(qb), max(3, args.steps // 2), 1)
+        batched = {"nrhs": nb_rhs, "value": n * nb_rhs / (msb * 1e-3) / 1e6, "ms_per_step": msb}
+        if not args.no_cpu:
+            ob = pb.matvec(qb)[3].cpu().numpy().astype(np.complex128)
+            qh = wl.plane_wave_charges(x, args.kappa, nb_rhs, seed=2)[3]
+            refb = direct.matvec(x, qh, args.kappa, targets=tg[:512])
+            batched["rel_err_rhs3"] = float(np.linalg.norm(ob[tg[:512]] - refb) / np.linalg.norm(refb))
+        log("batched %d rhs: %.3f ms (%.1f Mpoints/s)" % (nb_rhs, msb, batched["value"]))
+        del pb
+        torch.cuda.empty_cache()
+
+    large = None
+    if args.large:
+        nl = 1 << 23
+        xl = wl.ellipsoid_points(nl, seed=0)
+        ql = wl.complex_normal(nl, seed=1, nrhs=4)
+        xlt = torch.as_tensor(xl, dtype=torch.float64, device=dev)
+        qlt = torch.as_tensor(ql, dtype=torch.complex128, device=dev).to(torch.complex64)
+        t0 = time.perf_counter()
+        pl = ff.Plan(xlt, 500.0, 1e-3, precision="fp32", max_rhs=4)
+        torch.cuda.synchronize()
+        sl = time.perf_counter() - t0
+        msl = timed(lambda: pl.matvec(qlt), 3, 1)
+        il = pl.info()
+        large = {"n": nl, "nrhs": 4, "value": nl * 4 / (msl * 1e-3) / 1e6, "ms_per_step": msl,
+                 "setup_s": sl, "depth": il["depth"]}
+        if not args.no_cpu:
+            tl = wl.subset(nl, 256, seed=7)
+            ol = pl.matvec(qlt)[0].cpu().numpy().astype(np.complex128)
+            refl = direct.matvec(xl, ql[0], 500.0, targets=tl)
+            large["rel_err"] = float(np.linalg.norm(ol[tl] - refl) / np.linalg.norm(refl))
+        log("large: %s" % large)
+        del pl
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         del plan
@@ -207,6 +253,8 @@ def main():
         "setup_s": setup_s,
         "stages_ms": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
         "fp64": fp64,
+        "batched": batched,
+        "large": large,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
