@@ -150,20 +150,21 @@ __global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* _
 
 // ------------------------------------------------------------------------------------------
 // M2L (Transfer pass, Section 2): I_b(s_k) = sum_{e in I(b)} M_src(e)(s_k) T_off(e)(s_k).
-// Block: one target box, 256 directions; the interaction list is staged in LDS.
+// Block: one target box, 256 directions; the interaction list is staged in LDS; each T value read
+// serves RB right-hand sides.
 // ------------------------------------------------------------------------------------------
-template <class C>
+template <class C, int RB>
 __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
                                                   const int32_t* __restrict__ il_ptr,
                                                   const int32_t* __restrict__ il_src,
                                                   const int32_t* __restrict__ il_tix,
                                                   const C* __restrict__ T, const C* __restrict__ M,
-                                                  C* __restrict__ out, int64_t nb)
+                                                  C* __restrict__ out, int64_t nb, int nrhs)
 {
     __shared__ int32_t s_src[192], s_tix[192];
     const int64_t b = blockIdx.x / kchunks;
     const int k = (blockIdx.x % kchunks) * 256 + threadIdx.x;
-    const int64_t r = blockIdx.y;
+    const int r0 = blockIdx.y * RB;
     const int e0 = il_ptr[b], ne = il_ptr[b + 1] - e0;
     for (int t = threadIdx.x; t < ne; t += 256) {
         s_src[t] = il_src[e0 + t];
@@ -171,11 +172,20 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
     }
     __syncthreads();
     if (k >= K) return;
-    const C* Mr = M + r * nb * K + k;
+    const int64_t plane = nb * (int64_t)K;
+    const C* Mk = M + k;
     const C* Tk = T + k;
-    C acc = cz<C>();
-    for (int e = 0; e < ne; ++e) cmac(acc, Mr[(int64_t)s_src[e] * K], Tk[(int64_t)s_tix[e] * K]);
-    out[(r * nb + b) * K + k] = acc;
+    C acc[RB];
+    for (int q = 0; q < RB; ++q) acc[q] = cz<C>();
+    for (int e = 0; e < ne; ++e) {
+        const C t = Tk[(int64_t)s_tix[e] * K];
+        const C* m = Mk + (int64_t)s_src[e] * K;
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (r0 + q < nrhs) cmac(acc[q], m[(int64_t)(r0 + q) * plane], t);
+    }
+    for (int q = 0; q < RB; ++q)
+        if (r0 + q < nrhs) out[(int64_t)(r0 + q) * plane + b * K + k] = acc[q];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -282,20 +292,20 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
     constexpr int NC = GRAD ? 3 : 1;
     __shared__ double sx[kWave], sy[kWave], sz[kWave];
     __shared__ C sq[kWave];
+    __shared__ C part[NC][kWave];
     const int64_t b = blockIdx.x;
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x;
     const int tb = start[b], tc = count[b];
     const double kappa_rev = kappa / kTwoPi;
     for (int t0 = 0; t0 < tc; t0 += kWave) {
-        const bool valid = t0 + lane < tc;
-        const int64_t i = tb + t0 + lane;
-        double xi = 0, yi = 0, zi = 0;
-        if (valid) {
-            xi = xs[3 * i];
-            yi = xs[3 * i + 1];
-            zi = xs[3 * i + 2];
-        }
+        // g lanes per target split its sources: chunks of few targets keep the wave busy
+        const int tcnt = min(kWave, tc - t0);
+        const int g = kWave / tcnt;
+        const int my = lane / g, sub = lane % g;
+        const bool valid = my < tcnt;
+        const int64_t i = tb + t0 + (valid ? my : 0);
+        const double xi = xs[3 * i], yi = xs[3 * i + 1], zi = xs[3 * i + 2];
         C acc[NC];
         for (int a = 0; a < NC; ++a) acc[a] = cz<C>();
         for (int e = nb_ptr[b]; e < nb_ptr[b + 1]; ++e) {
@@ -313,7 +323,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
                 }
                 __syncthreads();
                 if (!valid) continue;
-                for (int t = 0; t < ns; ++t) {
+                for (int t = sub; t < ns; t += g) {
                     const int64_t j = sb + s0 + t;
                     const double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
                     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -344,11 +354,11 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
                         const R kr = (R)(kappa * rr);
                         const R inv3 = inv * inv * inv;
                         const R gr = (-c - s * kr) * inv3, gi = (c * kr - s) * inv3;
-                        C g = cmul(cmk<C>(gr, gi), sq[t]);
+                        const C gq = cmul(cmk<C>(gr, gi), sq[t]);
                         const R d[3] = {(R)dx, (R)dy, (R)dz};
                         for (int a = 0; a < 3; ++a) {
-                            acc[a].x += d[a] * g.x;
-                            acc[a].y += d[a] * g.y;
+                            acc[a].x += d[a] * gq.x;
+                            acc[a].y += d[a] * gq.y;
                         }
                     } else {
                         cmac(acc[0], cmk<C>(c * inv, s * inv), sq[t]);
@@ -356,12 +366,21 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
                 }
             }
         }
-        if (valid)
+        // combine the g partial sums of every target
+        for (int a = 0; a < NC; ++a) part[a][lane] = acc[a];
+        __syncthreads();
+        if (valid && sub == 0)
             for (int a = 0; a < NC; ++a) {
+                C sum = part[a][lane];
+                for (int u = 1; u < g; ++u) {
+                    sum.x += part[a][lane + u].x;
+                    sum.y += part[a][lane + u].y;
+                }
                 C& o = out[(r * n + i) * NC + a];
-                o.x += acc[a].x;
-                o.y += acc[a].y;
+                o.x += sum.x;
+                o.y += sum.y;
             }
+        __syncthreads();
     }
 }
 
@@ -419,9 +438,15 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
             StageScope sc(p, l == L ? FFMM_PROF_LEAF_M2L : FFMM_PROF_M2L, s);
             LevelData& Lv = p->lev[l];
             const int kch = (Lv.K + 255) / 256;
-            hipLaunchKernelGGL((m2l_kernel<C>), dim3((unsigned)(Lv.n * kch), nrhs), dim3(256), 0, s, Lv.K,
-                               kch, Lv.il_ptr, Lv.il_src, Lv.il_tix, (const C*)Lv.transfer,
-                               (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n);
+            const unsigned gx = (unsigned)(Lv.n * kch);
+            if (nrhs >= 4)
+                hipLaunchKernelGGL((m2l_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), dim3(256), 0, s,
+                                   Lv.K, kch, Lv.il_ptr, Lv.il_src, Lv.il_tix, (const C*)Lv.transfer,
+                                   (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+            else
+                hipLaunchKernelGGL((m2l_kernel<C, 1>), dim3(gx, nrhs), dim3(256), 0, s, Lv.K, kch,
+                                   Lv.il_ptr, Lv.il_src, Lv.il_tix, (const C*)Lv.transfer,
+                                   (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
             FFMM_LAUNCH_CHECK();
         }
         // L2L, l = 2..L-1 (translate on the parent grid, five-step resample, add to I)
