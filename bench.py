@@ -39,6 +39,8 @@ def parse():
                     help="leaf level (0: the plan's own choice from max_leaf and eps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (PMC calibration)")
     ap.add_argument("--large", action="store_true",
                     help="also run 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS")
     ap.add_argument("--no-cpu", action="store_true")
@@ -92,6 +94,15 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+        return
     import paper_0911_4114_amd as ff
     from paper_0911_4114_amd import workloads as wl
 

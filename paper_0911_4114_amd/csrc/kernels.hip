@@ -74,6 +74,17 @@ template <class R> __device__ inline void two_sum(R a, R b, R& s, R& e)
 
 template <class R> __device__ inline R shfl_down(R v, int d) { return __shfl_down(v, d, kWave); }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2. This bijection of
+// [0, nblocks) gives every XCD a contiguous range of logical blocks, so Morton-adjacent boxes
+// (which share interaction-list sources and neighbours) are served by one L2.
+__device__ inline unsigned xcd_block(unsigned b, unsigned nblocks)
+{
+    constexpr unsigned kXcd = 8;
+    const unsigned per = nblocks / kXcd, rem = nblocks % kXcd;
+    const unsigned x = b % kXcd, i = b / kXcd;
+    return x * per + min(x, rem) + i;
+}
+
 // ------------------------------------------------------------------------------------------
 // permutation with optional conjugation
 // ------------------------------------------------------------------------------------------
@@ -116,8 +127,9 @@ __global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* _
 {
     __shared__ R sx[256], sy[256], sz[256];
     __shared__ C sq[256];
-    const int64_t b = blockIdx.x / kchunks;
-    const int k = (blockIdx.x % kchunks) * 256 + threadIdx.x;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t b = lb / kchunks;
+    const int k = (lb % kchunks) * 256 + threadIdx.x;
     const int64_t r = blockIdx.y;
     R dx = 0, dy = 0, dz = 0;
     if (k < K) {
@@ -162,8 +174,9 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
                                                   C* __restrict__ out, int64_t nb, int nrhs)
 {
     __shared__ int32_t s_src[192], s_tix[192];
-    const int64_t b = blockIdx.x / kchunks;
-    const int k = (blockIdx.x % kchunks) * 256 + threadIdx.x;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t b = lb / kchunks;
+    const int k = (lb % kchunks) * 256 + threadIdx.x;
     const int r0 = blockIdx.y * RB;
     const int e0 = il_ptr[b], ne = il_ptr[b + 1] - e0;
     for (int t = threadIdx.x; t < ne; t += 256) {
@@ -208,7 +221,7 @@ __global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__
     constexpr int NC = GRAD ? 3 : 1;
     __shared__ R sx[kL2PChunk], sy[kL2PChunk], sz[kL2PChunk];
     __shared__ C swl[kL2PChunk];
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x;
     const int s0 = start[b], cnt = count[b];
@@ -293,7 +306,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
     __shared__ double sx[kWave], sy[kWave], sz[kWave];
     __shared__ C sq[kWave];
     __shared__ C part[NC][kWave];
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
     const int64_t r = blockIdx.y;
     const int lane = threadIdx.x;
     const int tb = start[b], tc = count[b];
