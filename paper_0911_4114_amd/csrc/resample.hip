@@ -303,6 +303,312 @@ __global__ __launch_bounds__(NT) void rs5_gemm(
     }
 }
 
+// ---- FP32 on the matrix cores ------------------------------------------------------------------
+// The same three contractions with v_mfma_f32_32x32x2f32 (FP32 products and sums, so the results
+// carry the same rounding model as the vector path). Operand lanes: A[i][k] and B[k][j] with
+// i, j = lane % 32 and k = lane / 32; result register q of a lane holds row
+// (q / 4) * 8 + (lane / 32) * 4 + q % 4 and column lane % 32 of the 32 x 32 tile.
+// A block is four waves on a 64 x 64 tile (each wave a 32 x 32 quadrant), with 16-deep k slabs
+// double-buffered in LDS (one barrier per slab).
+//   steps 1 and 5: rows are (box, re/im) pairs, columns the output samples of one row, so the
+//                  two registers q = 2p, 2p + 1 of a lane hold the (re, im) of one output and a
+//                  wave stores 32 consecutive complex samples;
+//   steps 2 + 3:   rows are the output theta_t', columns (box, phi_m, re/im).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MM = 64, MN = 64, MK = 16;
+constexpr int MAP = MM + 2;   // LDS row stride of the A slab (conflict-free 8-byte stores)
+constexpr int MBP = MN;       // LDS row stride of the B slab
+
+__device__ inline void mfma_slab(const float* __restrict__ As, const float* __restrict__ Bs, f32x16& acc,
+                                 int wr, int wc, int lane)
+{
+    const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int kk = 0; kk < MK; kk += 2) {
+        const float a = As[(kk + kh) * MAP + wr + i];
+        const float b = Bs[(kk + kh) * MBP + wc + i];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+}
+
+// box (0..31 within the block tile) of result pair p (registers 2p, 2p + 1) of this lane
+__device__ inline int pair_box(int wr, int lane, int p) { return wr / 2 + (p >> 1) * 4 + (lane >> 5) * 2 + (p & 1); }
+
+template <bool DOWN>
+__global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int ntj,
+                                               const int32_t* __restrict__ row_off,
+                                               const int32_t* __restrict__ nphi,
+                                               const float* __restrict__ d1,
+                                               const float2* __restrict__ sig, int Ksrc, int64_t nb_in,
+                                               const int32_t* __restrict__ parent,
+                                               const int32_t* __restrict__ octant,
+                                               const float2* __restrict__ trans, float2* __restrict__ G1)
+{
+    __shared__ __align__(16) float As[2][MK * MAP];
+    __shared__ __align__(16) float Bs[2][MK * MBP];
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
+    const int64_t r = blockIdx.z;
+    const int len = nphi[row], off = row_off[row];
+    const int64_t c0 = (int64_t)blockIdx.x * (MM / 2);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    float2 ra[2];
+    float4 rb;
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q, kk = e & (MK - 1), bc = e >> 4;
+            const int k = k0 + kk;
+            const int64_t c = c0 + bc;
+            float2 v = make_float2(0.f, 0.f);
+            if (k < len && c < nb) {
+                const int64_t cin = DOWN ? (int64_t)parent[c] : c;
+                v = sig[(r * nb_in + cin) * Ksrc + off + k];
+                if (DOWN) {
+                    const float2 t = trans[(int64_t)octant[c] * Ksrc + off + k];
+                    v = make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
+                }
+            }
+            ra[q] = v;
+        }
+        const int k = k0 + (tid >> 4), j = j0 + 4 * (tid & 15);
+        rb = (k < len && j < NA) ? *(const float4*)(d1 + (int64_t)(off + k) * NA + j)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q;
+            *(float2*)&As[buf][(e & (MK - 1)) * MAP + 2 * (e >> 4)] = ra[q];
+        }
+        *(float4*)&Bs[buf][(tid >> 4) * MBP + 4 * (tid & 15)] = rb;
+    };
+    f32x16 acc = {};
+    const int nslab = (len + MK - 1) / MK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        if (sl + 1 < nslab) load((sl + 1) * MK);
+        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
+        if (sl + 1 < nslab) store((sl + 1) & 1);
+        __syncthreads();
+    }
+    const int j = j0 + wc + (lane & 31);
+    if (j >= NA) return;
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) {
+        const int64_t c = c0 + pair_box(wr, lane, pq);
+        if (c < nb) G1[((r * nb + c) * rows + row) * NA + j] = make_float2(acc[2 * pq], acc[2 * pq + 1]);
+    }
+}
+
+__global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, int ntS, int ntD,
+                                               const float* __restrict__ dth,
+                                               const float2* __restrict__ G1, float2* __restrict__ G2)
+{
+    __shared__ __align__(16) float As[2][MK * MAP];
+    __shared__ __align__(16) float Bs[2][MK * MBP];
+    const int half = NA / 2;
+    const int i0 = blockIdx.y * MM;
+    const int64_t r = blockIdx.z;
+    const int64_t ncols = nb * half;
+    const int64_t g0 = (int64_t)blockIdx.x * (MN / 2);
+    const int64_t cbase = g0 / half;   // first (box, column) of the tile
+    const int m0 = (int)(g0 - cbase * half);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    // this thread's two staged columns never change: resolve (box, phi index) once
+    int64_t scol[2];
+    int sm[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int cc = (tid + NT * q) & 31;
+        int m = m0 + cc;
+        int64_t c = cbase;
+        while (m >= half) {
+            m -= half;
+            ++c;
+        }
+        scol[q] = c;
+        sm[q] = m;
+    }
+    float ra[4];
+    float2 rbv[2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + NT * q, i = e & 63, kk = e >> 6;
+            const int t = k0 + kk, tp = i0 + i;
+            ra[q] = (t < ntS && tp < ntD) ? dth[(int64_t)t * ntD + tp] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q, cc = e & 31, kk = e >> 5;
+            const int t = k0 + kk;
+            float2 v = make_float2(0.f, 0.f);
+            if (t < ntS && g0 + cc < ncols) {
+                const float2* base = G1 + (r * nb + scol[q]) * rowsS * NA;
+                v = (t <= ntS / 2) ? base[(int64_t)t * NA + sm[q]]
+                                   : base[(int64_t)(ntS - t) * NA + sm[q] + half];
+            }
+            rbv[q] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + NT * q;
+            As[buf][(e >> 6) * MAP + (e & 63)] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q;
+            *(float2*)&Bs[buf][(e >> 5) * MBP + 2 * (e & 31)] = rbv[q];
+        }
+    };
+    f32x16 acc = {};
+    const int nslab = (ntS + MK - 1) / MK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        if (sl + 1 < nslab) load((sl + 1) * MK);
+        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
+        if (sl + 1 < nslab) store((sl + 1) & 1);
+        __syncthreads();
+    }
+    const int col = wc + (lane & 31), cc = col >> 1, part = col & 1;
+    if (g0 + cc >= ncols) return;
+    int m = m0 + cc;
+    int64_t c = cbase;
+    while (m >= half) {
+        m -= half;
+        ++c;
+    }
+    float* base = (float*)(G2 + (r * nb + c) * ntD * half + m) + part;
+    const int h = lane >> 5;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int tp = i0 + wr + (q >> 2) * 8 + h * 4 + (q & 3);
+        if (tp < ntD) base[(int64_t)tp * half * 2] = acc[q];
+    }
+}
+
+template <bool UP>
+__global__ __launch_bounds__(NT) void rs5_mfma(
+    int64_t nb, int NA, int ntD, int ntj, const int32_t* __restrict__ row_off,
+    const int32_t* __restrict__ nphi, const float* __restrict__ d5, const float2* __restrict__ G2, int Kd,
+    const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
+    const int32_t* __restrict__ parent, const int32_t* __restrict__ octant,
+    const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_count,
+    const float2* __restrict__ trans, int64_t nb_out, float2* __restrict__ out)
+{
+    __shared__ __align__(16) float As[2][MK * MAP];
+    __shared__ __align__(16) float Bs[2][MK * MBP];
+    __shared__ float2 S[UP ? (MM / 2) * MN : 1];
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
+    const int64_t r = blockIdx.z;
+    const int len = nphi[row], off = row_off[row];
+    if (j0 >= len) return;
+    int64_t cb, ce;
+    if (UP) {
+        cb = tile_begin[blockIdx.x];
+        ce = tile_end[blockIdx.x];
+    } else {
+        cb = (int64_t)blockIdx.x * (MM / 2);
+        ce = min(cb + MM / 2, nb);
+    }
+    const int half = NA / 2;
+    const int tneg = (ntD - row) % ntD;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const float* D = d5 + (int64_t)off * NA;
+    float2 ra[2];
+    float4 rb;
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q, kk = e & (MK - 1), bc = e >> 4;
+            const int j = k0 + kk;
+            const int64_t c = cb + bc;
+            float2 v = make_float2(0.f, 0.f);
+            if (j < NA && c < ce) {
+                const float2* g = G2 + (r * nb + c) * ntD * half;
+                v = (j < half) ? g[(int64_t)row * half + j] : g[(int64_t)tneg * half + (j - half)];
+            }
+            ra[q] = v;
+        }
+        const int j = k0 + (tid >> 4), jp = j0 + 4 * (tid & 15);
+        rb = (j < NA && jp < len) ? *(const float4*)(D + (int64_t)j * len + jp)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + NT * q;
+            *(float2*)&As[buf][(e & (MK - 1)) * MAP + 2 * (e >> 4)] = ra[q];
+        }
+        *(float4*)&Bs[buf][(tid >> 4) * MBP + 4 * (tid & 15)] = rb;
+    };
+    f32x16 acc = {};
+    const int nslab = (NA + MK - 1) / MK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        if (sl + 1 < nslab) load((sl + 1) * MK);
+        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
+        if (sl + 1 < nslab) store((sl + 1) & 1);
+        __syncthreads();
+    }
+    const int colw = wc + (lane & 31);
+    const int jp = j0 + colw;
+    if (!UP) {
+        if (jp >= len) return;
+#pragma unroll
+        for (int pq = 0; pq < 8; ++pq) {
+            const int64_t c = cb + pair_box(wr, lane, pq);
+            if (c >= ce) continue;
+            float2& o = out[(r * nb_out + c) * Kd + off + jp];
+            o.x += acc[2 * pq];
+            o.y += acc[2 * pq + 1];
+        }
+        return;
+    }
+    // UP: translate each child on the parent grid, then sum the children of every parent
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) {
+        const int bx = pair_box(wr, lane, pq);
+        const int64_t c = cb + bx;
+        float2 v = make_float2(0.f, 0.f);
+        if (jp < len && c < ce) {
+            const float2 t = trans[(int64_t)octant[c] * Kd + off + jp];
+            const float x = acc[2 * pq], y = acc[2 * pq + 1];
+            v = make_float2(x * t.x - y * t.y, x * t.y + y * t.x);
+        }
+        S[bx * MN + colw] = v;
+    }
+    __syncthreads();
+    const int64_t p0 = parent[cb], p1 = parent[ce - 1];
+    const int npar = (int)(p1 - p0 + 1);
+    for (int e = tid; e < MN * npar; e += NT) {
+        const int i = e % MN, pi = e / MN;
+        const int jj = j0 + i;
+        if (jj >= len) continue;
+        const int64_t pp = p0 + pi;
+        const int64_t a = child_start[pp], cnt = child_count[pp];
+        float2 sum = make_float2(0.f, 0.f);
+        for (int64_t c = a; c < a + cnt; ++c) {
+            const float2 v = S[(int)(c - cb) * MN + i];
+            sum.x += v.x;
+            sum.y += v.y;
+        }
+        out[(r * nb_out + pp) * Kd + off + jj] = sum;
+    }
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <class R>
@@ -366,7 +672,8 @@ void run_resample_t(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
 
 }  // namespace
 
-// Child tiles of the upward pass: consecutive whole parents, at most 32 children per tile.
+// Child tiles of the upward pass: consecutive whole parents, at most 32 children per tile (the
+// box rows of one tile of either resample path).
 void make_parent_tiles(const std::vector<int32_t>& child_count, std::vector<int32_t>& begin,
                        std::vector<int32_t>& end)
 {
@@ -390,10 +697,69 @@ void make_parent_tiles(const std::vector<int32_t>& child_count, std::vector<int3
     }
 }
 
+namespace {
+
+void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
+{
+    const bool up = l_dst == l_src - 1;
+    Resampler& rs = up ? p->up[l_src] : p->down[l_src];
+    LevelData& S = p->lev[l_src];
+    LevelData& D = p->lev[l_dst];
+    LevelData& Cl = up ? S : D;
+    float2* G1 = (float2*)p->scratch1;
+    float2* G2 = (float2*)p->scratch2;
+    const int NA = rs.nphi_all;
+    const int64_t nb = Cl.n;
+    {
+        const int ntj = cdiv(NA, MN);
+        dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_src, nrhs);
+        if (up)
+            hipLaunchKernelGGL((rs1_mfma<false>), grid, dim3(NT), 0, s, nb, rs.rows_src, NA, ntj,
+                               rs.d_src_row_off, rs.d_src_nphi, (const float*)rs.d1,
+                               (const float2*)S.sigM, S.K, S.n, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, (const float2*)nullptr, G1);
+        else
+            hipLaunchKernelGGL((rs1_mfma<true>), grid, dim3(NT), 0, s, nb, rs.rows_src, NA, ntj,
+                               rs.d_src_row_off, rs.d_src_nphi, (const float*)rs.d1,
+                               (const float2*)S.sigL, S.K, S.n, Cl.parent, Cl.octant,
+                               (const float2*)S.trans, G1);
+        FFMM_LAUNCH_CHECK();
+    }
+    {
+        dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(rs.nt_dst, MM), nrhs);
+        hipLaunchKernelGGL(rs3_mfma, grid, dim3(NT), 0, s, nb, NA, rs.rows_src, rs.nt_src, rs.nt_dst,
+                           (const float*)rs.dth, (const float2*)G1, G2);
+        FFMM_LAUNCH_CHECK();
+    }
+    {
+        int mx = 0;
+        for (int v : D.par.nphi) mx = std::max(mx, v);
+        const int ntj = cdiv(mx, MN);
+        if (up) {
+            dim3 grid((unsigned)rs.ntiles, ntj * rs.rows_dst, nrhs);
+            hipLaunchKernelGGL((rs5_mfma<true>), grid, dim3(NT), 0, s, nb, NA, rs.nt_dst, ntj,
+                               rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5, (const float2*)G2,
+                               D.K, rs.tile_begin, rs.tile_end, Cl.parent, Cl.octant, D.child_start,
+                               D.child_count, (const float2*)D.trans, D.n, (float2*)D.sigM);
+        } else {
+            dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_dst, nrhs);
+            hipLaunchKernelGGL((rs5_mfma<false>), grid, dim3(NT), 0, s, nb, NA, rs.nt_dst, ntj,
+                               rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5, (const float2*)G2,
+                               D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, (const int32_t*)nullptr,
+                               (const float2*)nullptr, D.n, (float2*)D.sigL);
+        }
+        FFMM_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace
+
 void run_resample(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
 {
     if (p->prec == FFMM_FP32)
-        run_resample_t<float>(p, l_src, l_dst, nrhs, s);
+        run_resample_mfma(p, l_src, l_dst, nrhs, s);
     else
         run_resample_t<double>(p, l_src, l_dst, nrhs, s);
 }
