@@ -18,11 +18,16 @@ import numpy as np
 from .fourier import resample_1d
 
 
-def resample_sig(f, q_src, q_dst):
-    """Five-step resample of signatures f [..., K_src] from q_src to q_dst. Returns [..., K_dst]."""
+def resample_sig(f, q_src, q_dst, nphi_all=None):
+    """Five-step resample of signatures f [..., K_src] from q_src to q_dst. Returns [..., K_dst].
+
+    nphi_all is the common phi length NPhi of steps 1-5 (default: the largest row length of either
+    quadrature, as in Section 3.4). Tests pass other even lengths to check which of them give the
+    same operator."""
     f = np.asarray(f, dtype=np.complex128)
     lead = f.shape[:-1]
-    nphi_all = max(int(q_src.nphi.max()), int(q_dst.nphi.max()))
+    if nphi_all is None:
+        nphi_all = max(int(q_src.nphi.max()), int(q_dst.nphi.max()))
     half = nphi_all // 2
     nt, nt2 = q_src.ntheta, q_dst.ntheta
     # step 1

@@ -76,12 +76,13 @@ struct LevelData {
 
 // Dense real Fourier-resample operators between two level quadratures (Section 3.4).
 struct Resampler {
-    int nphi_all = 0;               // largest row length of both quadratures
+    int nphi_all = 0;               // common phi length: min of the two quadratures' largest rows
     int nt_src = 0, nt_dst = 0;
     int rows_src = 0, rows_dst = 0;
     int K_src = 0, K_dst = 0;
     void* d1 = nullptr;             // step 1, per source row n: [N_phi,n][nphi_all] (j fastest)
-    void* dth = nullptr;            // step 3: [nt_src][nt_dst] (t' fastest)
+    void* dth = nullptr;            // step 3: [nt_src][nt_dth] (t' fastest, zero-padded)
+    int nt_dth = 0;                 // row stride of dth: nt_dst rounded up to a multiple of 4
     void* d5 = nullptr;             // step 5, per dest row n': [nphi_all][N'_phi,n'] (j' fastest)
     int32_t* d_src_row_off = nullptr;
     int32_t* d_src_nphi = nullptr;

@@ -317,9 +317,14 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
 template <class R>
 void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resampler& rs, hipStream_t s)
 {
-    int na = 0;
-    for (int v : S.par.nphi) na = std::max(na, v);
-    for (int v : D.par.nphi) na = std::max(na, v);
+    // Common phi length of steps 1-5: the smaller of the two largest row lengths. Upward the source
+    // rows fit on it without loss, downward the destination rows keep no mode it lacks, and the
+    // theta step acts on each phi mode separately; on data with the doubled-sphere symmetry (every
+    // signature) this gives the same operator as the largest row length of either grid.
+    int na_s = 0, na_d = 0;
+    for (int v : S.par.nphi) na_s = std::max(na_s, v);
+    for (int v : D.par.nphi) na_d = std::max(na_d, v);
+    const int na = std::min(na_s, na_d);
     rs.nphi_all = na;
     rs.nt_src = S.par.ntheta;
     rs.nt_dst = D.par.ntheta;
@@ -327,7 +332,8 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     rs.rows_dst = D.nrows;
     rs.K_src = S.K;
     rs.K_dst = D.K;
-    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * rs.nt_dst), d5((size_t)D.K * na);
+    rs.nt_dth = (rs.nt_dst + 3) / 4 * 4;
+    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * rs.nt_dth, 0.0), d5((size_t)D.K * na);
     for (int n = 0; n < S.nrows; ++n) {
         const int len = S.par.nphi[n];
         double* blk = &d1[(size_t)S.row_off[n] * na];
@@ -336,7 +342,7 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     }
     for (int t = 0; t < rs.nt_src; ++t)
         for (int tp = 0; tp < rs.nt_dst; ++tp)
-            dth[(size_t)t * rs.nt_dst + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
+            dth[(size_t)t * rs.nt_dth + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
     for (int n = 0; n < D.nrows; ++n) {
         const int len = D.par.nphi[n];
         double* blk = &d5[(size_t)D.row_off[n] * na];

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) void rs1_gemm(int64_t nb, int rows, int NA, int
 // steps 2 + 3 --------------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(NT) void rs3_gemm(int64_t nb, int NA, int rowsS, int ntS, int ntD,
-                                               const R* __restrict__ dth,
+                                               int ldth, const R* __restrict__ dth,
                                                const typename cpx<R>::type* __restrict__ G1,
                                                typename cpx<R>::type* __restrict__ G2)
 {
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NT) void rs3_gemm(int64_t nb, int NA, int rowsS, in
         for (int e = tid; e < BM * BK; e += NT) {
             const int i = e % BM, kk = e / BM;
             const int t = k0 + kk, tp = i0 + i;
-            As[kk * BM + i] = (t < ntS && tp < ntD) ? dth[(int64_t)t * ntD + tp] : R(0);
+            As[kk * BM + i] = (t < ntS && tp < ntD) ? dth[(int64_t)t * ldth + tp] : R(0);
         }
         for (int e = tid; e < BK * BC; e += NT) {
             const int cc = e % BC, kk = e / BC;
@@ -308,34 +308,117 @@ __global__ __launch_bounds__(NT) void rs5_gemm(
 // carry the same rounding model as the vector path). Operand lanes: A[i][k] and B[k][j] with
 // i, j = lane % 32 and k = lane / 32; result register q of a lane holds row
 // (q / 4) * 8 + (lane / 32) * 4 + q % 4 and column lane % 32 of the 32 x 32 tile.
-// A block is four waves on a 64 x 64 tile (each wave a 32 x 32 quadrant), with 16-deep k slabs
-// double-buffered in LDS (one barrier per slab).
+// A block is four waves on a 64 x 64 tile (each wave a 32 x 32 quadrant). The contraction runs in
+// KS-deep k slabs staged in LDS (KS = 16, 32 or 64 per kernel: deeper slabs keep more of a
+// block's data in flight, shallower ones waste less on short rows and allow more blocks per CU).
 //   steps 1 and 5: rows are (box, re/im) pairs, columns the output samples of one row, so the
 //                  two registers q = 2p, 2p + 1 of a lane hold the (re, im) of one output and a
 //                  wave stores 32 consecutive complex samples;
 //   steps 2 + 3:   rows are the output theta_t', columns (box, phi_m, re/im).
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int MM = 64, MN = 64, MK = 16;
-constexpr int MAP = MM + 2;   // LDS row stride of the A slab (conflict-free 8-byte stores)
+constexpr int MM = 64, MN = 64;
+constexpr int MAP = MM + 4;   // LDS row stride of the A slab (rows stay 16-byte aligned)
 constexpr int MBP = MN;       // LDS row stride of the B slab
 
+// acc += A[:, 0:kc] B[0:kc, :] for this wave's quadrant; kc is block-uniform, slab rows >= kc
+// hold zeros up to the next multiple of 8 (kc <= KS)
 __device__ inline void mfma_slab(const float* __restrict__ As, const float* __restrict__ Bs, f32x16& acc,
-                                 int wr, int wc, int lane)
+                                 int wr, int wc, int lane, int kc)
 {
     const int i = lane & 31, kh = lane >> 5;
+    for (int k8 = 0; k8 < kc; k8 += 8) {
+        float a[4], b[4];
 #pragma unroll
-    for (int kk = 0; kk < MK; kk += 2) {
-        const float a = As[(kk + kh) * MAP + wr + i];
-        const float b = Bs[(kk + kh) * MBP + wc + i];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+            a[u] = As[(k8 + 2 * u + kh) * MAP + wr + i];
+            b[u] = Bs[(k8 + 2 * u + kh) * MBP + wc + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
     }
 }
 
 // box (0..31 within the block tile) of result pair p (registers 2p, 2p + 1) of this lane
 __device__ inline int pair_box(int wr, int lane, int p) { return wr / 2 + (p >> 1) * 4 + (lane >> 5) * 2 + (p & 1); }
 
-template <bool DOWN>
+// Shared main loop over one LDS slab buffer. Stage::load(k0) issues the global loads of the slab
+// starting at k0 into registers; Stage::store(As, Bs) writes them (zeroing invalid entries) once
+// they have landed. The next slab's loads are in flight during the current slab's MFMAs.
+template <int KS, class Stage>
+__device__ inline void mfma_mainloop(Stage& st, float* As, float* Bs, int K, f32x16& acc, int wr, int wc,
+                                     int lane)
+{
+    const int nslab = (K + KS - 1) / KS;
+    st.load(0);
+    st.store(As, Bs);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        const bool more = sl + 1 < nslab;
+        if (more) st.load((sl + 1) * KS);
+        const int kc = min(KS, K - sl * KS);
+        mfma_slab(As, Bs, acc, wr, wc, lane, (kc + 7) & ~7);
+        if (more) {
+            __syncthreads();   // every wave is done with this slab
+            st.store(As, Bs);
+        }
+        __syncthreads();
+    }
+}
+
+// step 1 staging: A = source row data of 32 boxes (optionally parent data times conj(E_oct)),
+// B = the Dirichlet block of the row
+template <bool DOWN, int KS> struct Rs1Stage {
+    int tid, len, off, Ksrc, NA, j0;
+    int64_t c0, nb, nb_in, r;
+    const float2* sig;
+    const int32_t* parent;
+    const int32_t* octant;
+    const float2* trans;
+    const float* d1;
+    static constexpr int QA = KS / 8, QB = KS / 16;
+    float2 ra[QA];
+    float4 rb[QB];
+    bool oka[QA], okb[QB];
+    __device__ void load(int k0)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q, kk = e % KS, bc = e / KS;
+            const int k = min(k0 + kk, len - 1);
+            const int64_t c = min(c0 + bc, nb - 1);
+            const int64_t cin = DOWN ? (int64_t)parent[c] : c;
+            float2 v = sig[(r * nb_in + cin) * Ksrc + off + k];
+            if (DOWN) {
+                const float2 t = trans[(int64_t)octant[c] * Ksrc + off + k];
+                v = make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
+            }
+            ra[q] = v;
+            oka[q] = k0 + kk < len && c0 + bc < nb;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q, kr = k0 + (e >> 4), j = j0 + 4 * (e & 15);
+            rb[q] = *(const float4*)(d1 + (int64_t)(off + min(kr, len - 1)) * NA + (j < NA ? j : 0));
+            okb[q] = kr < len && j < NA;
+        }
+    }
+    __device__ void store(float* As, float* Bs)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = oka[q] ? ra[q] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q;
+            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] = okb[q] ? rb[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+};
+
+template <bool DOWN, int KS>
 __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int ntj,
                                                const int32_t* __restrict__ row_off,
                                                const int32_t* __restrict__ nphi,
@@ -345,71 +428,86 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int
                                                const int32_t* __restrict__ octant,
                                                const float2* __restrict__ trans, float2* __restrict__ G1)
 {
-    __shared__ __align__(16) float As[2][MK * MAP];
-    __shared__ __align__(16) float Bs[2][MK * MBP];
     const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
-    const int64_t r = blockIdx.z;
-    const int len = nphi[row], off = row_off[row];
-    const int64_t c0 = (int64_t)blockIdx.x * (MM / 2);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    float2 ra[2];
-    float4 rb;
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q, kk = e & (MK - 1), bc = e >> 4;
-            const int k = k0 + kk;
-            const int64_t c = c0 + bc;
-            float2 v = make_float2(0.f, 0.f);
-            if (k < len && c < nb) {
-                const int64_t cin = DOWN ? (int64_t)parent[c] : c;
-                v = sig[(r * nb_in + cin) * Ksrc + off + k];
-                if (DOWN) {
-                    const float2 t = trans[(int64_t)octant[c] * Ksrc + off + k];
-                    v = make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
-                }
-            }
-            ra[q] = v;
-        }
-        const int k = k0 + (tid >> 4), j = j0 + 4 * (tid & 15);
-        rb = (k < len && j < NA) ? *(const float4*)(d1 + (int64_t)(off + k) * NA + j)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q;
-            *(float2*)&As[buf][(e & (MK - 1)) * MAP + 2 * (e >> 4)] = ra[q];
-        }
-        *(float4*)&Bs[buf][(tid >> 4) * MBP + 4 * (tid & 15)] = rb;
-    };
+    __shared__ __align__(16) float As[KS * MAP];
+    __shared__ __align__(16) float Bs[KS * MBP];
+    Rs1Stage<DOWN, KS> st;
+    st.tid = tid;
+    st.len = nphi[row];
+    st.off = row_off[row];
+    st.Ksrc = Ksrc;
+    st.NA = NA;
+    st.j0 = j0;
+    st.c0 = (int64_t)blockIdx.x * (MM / 2);
+    st.nb = nb;
+    st.nb_in = nb_in;
+    st.r = blockIdx.z;
+    st.sig = sig;
+    st.parent = parent;
+    st.octant = octant;
+    st.trans = trans;
+    st.d1 = d1;
     f32x16 acc = {};
-    const int nslab = (len + MK - 1) / MK;
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int sl = 0; sl < nslab; ++sl) {
-        if (sl + 1 < nslab) load((sl + 1) * MK);
-        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
-        if (sl + 1 < nslab) store((sl + 1) & 1);
-        __syncthreads();
-    }
+    mfma_mainloop<KS>(st, As, Bs, st.len, acc, wr, wc, lane);
     const int j = j0 + wc + (lane & 31);
     if (j >= NA) return;
+    const int64_t r = blockIdx.z;
 #pragma unroll
     for (int pq = 0; pq < 8; ++pq) {
-        const int64_t c = c0 + pair_box(wr, lane, pq);
+        const int64_t c = st.c0 + pair_box(wr, lane, pq);
         if (c < nb) G1[((r * nb + c) * rows + row) * NA + j] = make_float2(acc[2 * pq], acc[2 * pq + 1]);
     }
 }
 
-__global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, int ntS, int ntD,
+// steps 2 + 3 staging: A = theta resample matrix (t' fastest), B = circle data of 32 columns
+template <int KS> struct Rs3Stage {
+    static constexpr int QA = KS / 16, QB = KS / 8;
+    int tid, ntS, ldth, i0, half, NA;
+    const float* dth;
+    const float2* sbase;   // this thread's staged column (phi_m of its box), row 0
+    bool scol_ok;
+    float4 ra[QA];
+    float2 rb[QB];
+    bool oka[QA], okb[QB];
+    __device__ void load(int k0)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q, t = k0 + (e >> 4), tp = i0 + 4 * (e & 15);
+            const bool ok = t < ntS && tp < ldth;
+            ra[q] = *(const float4*)(dth + (ok ? (int64_t)t * ldth + tp : 0));
+            oka[q] = ok;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int tt = k0 + (tid >> 5) + 8 * q;
+            const int t = min(tt, ntS - 1);
+            const bool lo = t <= ntS / 2;
+            rb[q] = sbase[(int64_t)(lo ? t : ntS - t) * NA + (lo ? 0 : half)];
+            okb[q] = tt < ntS && scol_ok;
+        }
+    }
+    __device__ void store(float* As, float* Bs)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            *(float4*)&As[(e >> 4) * MAP + 4 * (e & 15)] = oka[q] ? ra[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            *(float2*)&Bs[((tid >> 5) + 8 * q) * MBP + 2 * (tid & 31)] = okb[q] ? rb[q] : make_float2(0.f, 0.f);
+        }
+    }
+};
+
+template <int KS>
+__global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, int ntS, int ntD, int ldth,
                                                const float* __restrict__ dth,
                                                const float2* __restrict__ G1, float2* __restrict__ G2)
 {
-    __shared__ __align__(16) float As[2][MK * MAP];
-    __shared__ __align__(16) float Bs[2][MK * MBP];
     const int half = NA / 2;
     const int i0 = blockIdx.y * MM;
     const int64_t r = blockIdx.z;
@@ -419,66 +517,30 @@ __global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, in
     const int m0 = (int)(g0 - cbase * half);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    // this thread's two staged columns never change: resolve (box, phi index) once
-    int64_t scol[2];
-    int sm[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int cc = (tid + NT * q) & 31;
+    __shared__ __align__(16) float As[KS * MAP];
+    __shared__ __align__(16) float Bs[KS * MBP];
+    Rs3Stage<KS> st;
+    st.tid = tid;
+    st.ntS = ntS;
+    st.ldth = ldth;
+    st.i0 = i0;
+    st.half = half;
+    st.NA = NA;
+    st.dth = dth;
+    {
+        // the staged column of this thread: (box, phi index) of column g0 + tid % 32
+        const int cc = tid & 31;
         int m = m0 + cc;
         int64_t c = cbase;
         while (m >= half) {
             m -= half;
             ++c;
         }
-        scol[q] = c;
-        sm[q] = m;
+        st.scol_ok = g0 + cc < ncols;
+        st.sbase = st.scol_ok ? G1 + (r * nb + c) * rowsS * NA + m : G1;
     }
-    float ra[4];
-    float2 rbv[2];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + NT * q, i = e & 63, kk = e >> 6;
-            const int t = k0 + kk, tp = i0 + i;
-            ra[q] = (t < ntS && tp < ntD) ? dth[(int64_t)t * ntD + tp] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q, cc = e & 31, kk = e >> 5;
-            const int t = k0 + kk;
-            float2 v = make_float2(0.f, 0.f);
-            if (t < ntS && g0 + cc < ncols) {
-                const float2* base = G1 + (r * nb + scol[q]) * rowsS * NA;
-                v = (t <= ntS / 2) ? base[(int64_t)t * NA + sm[q]]
-                                   : base[(int64_t)(ntS - t) * NA + sm[q] + half];
-            }
-            rbv[q] = v;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + NT * q;
-            As[buf][(e >> 6) * MAP + (e & 63)] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q;
-            *(float2*)&Bs[buf][(e >> 5) * MBP + 2 * (e & 31)] = rbv[q];
-        }
-    };
     f32x16 acc = {};
-    const int nslab = (ntS + MK - 1) / MK;
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int sl = 0; sl < nslab; ++sl) {
-        if (sl + 1 < nslab) load((sl + 1) * MK);
-        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
-        if (sl + 1 < nslab) store((sl + 1) & 1);
-        __syncthreads();
-    }
+    mfma_mainloop<KS>(st, As, Bs, ntS, acc, wr, wc, lane);
     const int col = wc + (lane & 31), cc = col >> 1, part = col & 1;
     if (g0 + cc >= ncols) return;
     int m = m0 + cc;
@@ -496,7 +558,51 @@ __global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, in
     }
 }
 
-template <bool UP>
+// steps 4 + 5 staging: A = the destination row's samples on the common phi grid (rows n' and
+// N'_theta - n' of the theta-resampled data), B = the Dirichlet block of the destination row
+template <int KS> struct Rs5Stage {
+    static constexpr int QA = KS / 8, QB = KS / 16;
+    int tid, NA, half, row, tneg, ntD, len, j0;
+    int64_t cb, ce, nb, r;
+    const float2* G2;
+    const float* D;
+    float2 ra[QA];
+    float4 rb[QB];
+    bool oka[QA], okb[QB];
+    __device__ void load(int k0)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q, kk = e % KS, bc = e / KS;
+            const int j = min(k0 + kk, NA - 1);
+            const int64_t c = min(cb + bc, ce - 1);
+            const float2* g = G2 + (r * nb + c) * ntD * half;
+            ra[q] = (j < half) ? g[(int64_t)row * half + j] : g[(int64_t)tneg * half + (j - half)];
+            oka[q] = k0 + kk < NA && cb + bc < ce;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q, j = k0 + (e >> 4), jp = j0 + 4 * (e & 15);
+            rb[q] = *(const float4*)(D + (int64_t)min(j, NA - 1) * len + (jp < len ? jp : 0));
+            okb[q] = j < NA && jp < len;
+        }
+    }
+    __device__ void store(float* As, float* Bs)
+    {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = oka[q] ? ra[q] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + NT * q;
+            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] = okb[q] ? rb[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+};
+
+template <bool UP, int KS>
 __global__ __launch_bounds__(NT) void rs5_mfma(
     int64_t nb, int NA, int ntD, int ntj, const int32_t* __restrict__ row_off,
     const int32_t* __restrict__ nphi, const float* __restrict__ d5, const float2* __restrict__ G2, int Kd,
@@ -505,9 +611,6 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_count,
     const float2* __restrict__ trans, int64_t nb_out, float2* __restrict__ out)
 {
-    __shared__ __align__(16) float As[2][MK * MAP];
-    __shared__ __align__(16) float Bs[2][MK * MBP];
-    __shared__ float2 S[UP ? (MM / 2) * MN : 1];
     const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
     const int64_t r = blockIdx.z;
     const int len = nphi[row], off = row_off[row];
@@ -520,49 +623,29 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
         cb = (int64_t)blockIdx.x * (MM / 2);
         ce = min(cb + MM / 2, nb);
     }
-    const int half = NA / 2;
-    const int tneg = (ntD - row) % ntD;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    const float* D = d5 + (int64_t)off * NA;
-    float2 ra[2];
-    float4 rb;
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q, kk = e & (MK - 1), bc = e >> 4;
-            const int j = k0 + kk;
-            const int64_t c = cb + bc;
-            float2 v = make_float2(0.f, 0.f);
-            if (j < NA && c < ce) {
-                const float2* g = G2 + (r * nb + c) * ntD * half;
-                v = (j < half) ? g[(int64_t)row * half + j] : g[(int64_t)tneg * half + (j - half)];
-            }
-            ra[q] = v;
-        }
-        const int j = k0 + (tid >> 4), jp = j0 + 4 * (tid & 15);
-        rb = (j < NA && jp < len) ? *(const float4*)(D + (int64_t)j * len + jp)
-                                  : make_float4(0.f, 0.f, 0.f, 0.f);
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int e = tid + NT * q;
-            *(float2*)&As[buf][(e & (MK - 1)) * MAP + 2 * (e >> 4)] = ra[q];
-        }
-        *(float4*)&Bs[buf][(tid >> 4) * MBP + 4 * (tid & 15)] = rb;
-    };
+    // the A slab also holds the translated children (32 x 64 complex) in the upward pass
+    constexpr int kA = (UP && KS * MAP < 2 * (MM / 2) * MN) ? 2 * (MM / 2) * MN : KS * MAP;
+    __shared__ __align__(16) float As[kA];
+    __shared__ __align__(16) float Bs[KS * MBP];
+    Rs5Stage<KS> st;
+    st.tid = tid;
+    st.NA = NA;
+    st.half = NA / 2;
+    st.row = row;
+    st.tneg = (ntD - row) % ntD;
+    st.ntD = ntD;
+    st.len = len;
+    st.j0 = j0;
+    st.cb = cb;
+    st.ce = ce;
+    st.nb = nb;
+    st.r = r;
+    st.G2 = G2;
+    st.D = d5 + (int64_t)off * NA;
     f32x16 acc = {};
-    const int nslab = (NA + MK - 1) / MK;
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int sl = 0; sl < nslab; ++sl) {
-        if (sl + 1 < nslab) load((sl + 1) * MK);
-        mfma_slab(As[sl & 1], Bs[sl & 1], acc, wr, wc, lane);
-        if (sl + 1 < nslab) store((sl + 1) & 1);
-        __syncthreads();
-    }
+    mfma_mainloop<KS>(st, As, Bs, NA, acc, wr, wc, lane);
     const int colw = wc + (lane & 31);
     const int jp = j0 + colw;
     if (!UP) {
@@ -577,7 +660,9 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
         }
         return;
     }
-    // UP: translate each child on the parent grid, then sum the children of every parent
+    // UP: translate each child on the parent grid, then sum the children of every parent (the
+    // slabs are free after the main loop's last barrier)
+    float2* S = (float2*)As;   // 32 x 64 complex
 #pragma unroll
     for (int pq = 0; pq < 8; ++pq) {
         const int bx = pair_box(wr, lane, pq);
@@ -643,7 +728,7 @@ void run_resample_t(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
     {
         dim3 grid(cdiv(nb * (NA / 2), BC), cdiv(rs.nt_dst, BM), nrhs);
         hipLaunchKernelGGL((rs3_gemm<R>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src, rs.nt_src,
-                           rs.nt_dst, (const R*)rs.dth, (const C*)G1, G2);
+                           rs.nt_dst, rs.nt_dth, (const R*)rs.dth, (const C*)G1, G2);
         FFMM_LAUNCH_CHECK();
     }
     // steps 4 + 5
@@ -699,6 +784,23 @@ void make_parent_tiles(const std::vector<int32_t>& child_count, std::vector<int3
 
 namespace {
 
+template <int V> struct KsTag { static constexpr int value = V; };
+
+// runs f(KsTag<KS>{}) for the slab depth ks (16, 32 or 64)
+template <class F> void with_ks(int ks, F&& f)
+{
+    if (ks == 16)
+        f(KsTag<16>{});
+    else if (ks == 32)
+        f(KsTag<32>{});
+    else
+        f(KsTag<64>{});
+}
+
+// slab depth per kernel (measured on the 2^20-point sphere at kappa 177: the row steps favour
+// shallow slabs, the circle step and the upward step 5 deeper ones)
+constexpr int kKsRs1 = 16, kKsRs3 = 32, kKsRs5Up = 32, kKsRs5Down = 16;
+
 void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
 {
     const bool up = l_dst == l_src - 1;
@@ -714,21 +816,29 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ntj = cdiv(NA, MN);
         dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_src, nrhs);
         if (up)
-            hipLaunchKernelGGL((rs1_mfma<false>), grid, dim3(NT), 0, s, nb, rs.rows_src, NA, ntj,
-                               rs.d_src_row_off, rs.d_src_nphi, (const float*)rs.d1,
-                               (const float2*)S.sigM, S.K, S.n, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr, (const float2*)nullptr, G1);
+            with_ks(kKsRs1, [&](auto t) {
+                hipLaunchKernelGGL((rs1_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
+                                   rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
+                                   (const float*)rs.d1, (const float2*)S.sigM, S.K, S.n,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const float2*)nullptr, G1);
+            });
         else
-            hipLaunchKernelGGL((rs1_mfma<true>), grid, dim3(NT), 0, s, nb, rs.rows_src, NA, ntj,
-                               rs.d_src_row_off, rs.d_src_nphi, (const float*)rs.d1,
-                               (const float2*)S.sigL, S.K, S.n, Cl.parent, Cl.octant,
-                               (const float2*)S.trans, G1);
+            with_ks(kKsRs1, [&](auto t) {
+                hipLaunchKernelGGL((rs1_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
+                                   rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
+                                   (const float*)rs.d1, (const float2*)S.sigL, S.K, S.n, Cl.parent,
+                                   Cl.octant, (const float2*)S.trans, G1);
+            });
         FFMM_LAUNCH_CHECK();
     }
     {
         dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(rs.nt_dst, MM), nrhs);
-        hipLaunchKernelGGL(rs3_mfma, grid, dim3(NT), 0, s, nb, NA, rs.rows_src, rs.nt_src, rs.nt_dst,
-                           (const float*)rs.dth, (const float2*)G1, G2);
+        with_ks(kKsRs3, [&](auto t) {
+            hipLaunchKernelGGL((rs3_mfma<decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
+                               rs.nt_src, rs.nt_dst, rs.nt_dth, (const float*)rs.dth, (const float2*)G1,
+                               G2);
+        });
         FFMM_LAUNCH_CHECK();
     }
     {
@@ -737,18 +847,23 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ntj = cdiv(mx, MN);
         if (up) {
             dim3 grid((unsigned)rs.ntiles, ntj * rs.rows_dst, nrhs);
-            hipLaunchKernelGGL((rs5_mfma<true>), grid, dim3(NT), 0, s, nb, NA, rs.nt_dst, ntj,
-                               rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5, (const float2*)G2,
-                               D.K, rs.tile_begin, rs.tile_end, Cl.parent, Cl.octant, D.child_start,
-                               D.child_count, (const float2*)D.trans, D.n, (float2*)D.sigM);
+            with_ks(kKsRs5Up, [&](auto t) {
+                hipLaunchKernelGGL((rs5_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
+                                   rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5,
+                                   (const float2*)G2, D.K, rs.tile_begin, rs.tile_end, Cl.parent,
+                                   Cl.octant, D.child_start, D.child_count, (const float2*)D.trans, D.n,
+                                   (float2*)D.sigM);
+            });
         } else {
             dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_dst, nrhs);
-            hipLaunchKernelGGL((rs5_mfma<false>), grid, dim3(NT), 0, s, nb, NA, rs.nt_dst, ntj,
-                               rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5, (const float2*)G2,
-                               D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr, (const int32_t*)nullptr,
-                               (const float2*)nullptr, D.n, (float2*)D.sigL);
+            with_ks(kKsRs5Down, [&](auto t) {
+                hipLaunchKernelGGL((rs5_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
+                                   rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5,
+                                   (const float2*)G2, D.K, (const int32_t*)nullptr,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const int32_t*)nullptr, (const float2*)nullptr, D.n, (float2*)D.sigL);
+            });
         }
         FFMM_LAUNCH_CHECK();
     }

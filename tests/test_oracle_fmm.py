@@ -140,6 +140,33 @@ def test_every_pair_counted_once():
 
 # --- five-step resample ---------------------------------------------------------------------
 
+@pytest.mark.parametrize("ka_pair", [(2.0, 4.0), (4.0, 2.0), (7.5, 15.0), (15.0, 7.5)])
+def test_five_step_common_length_min_equals_max(ka_pair):
+    """The common phi length may be the smaller of the two largest row lengths: upward the source
+    rows already fit on it, downward the destination rows keep no mode it lacks, and the theta
+    step acts on each phi mode separately (the mirror multiplies mode p by (-1)^p). So the
+    five-step operator with NPhi = min equals the one with NPhi = max on data with the symmetry of
+    the doubled sphere (eqn. NumSphereSym), i.e. on every signature: the rows theta = 0 and
+    theta = pi are their own mirror images, so F(theta, phi) = F(theta, phi + pi) there."""
+    q1, _ = level_quadrature(ka_pair[0], 0.8, 1e-6)
+    q2, _ = level_quadrature(ka_pair[1], 0.8, 1e-6)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((2, q1.K)) + 1j * rng.standard_normal((2, q1.K))
+    for n in (0, q1.nrows - 1):   # project the self-mirrored rows onto pi-periodic data
+        a, b = q1.row_off[n], q1.row_off[n + 1]
+        row = f[:, a:b]
+        f[:, a:b] = 0.5 * (row + np.roll(row, (b - a) // 2, axis=-1))
+    n_lo = min(int(q1.nphi.max()), int(q2.nphi.max()))
+    n_hi = max(int(q1.nphi.max()), int(q2.nphi.max()))
+    assert n_lo < n_hi
+    ref = resample_sig(f, q1, q2)
+    got = resample_sig(f, q1, q2, nphi_all=n_lo)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # a common length below both maxima drops modes the destination keeps
+    bad = resample_sig(f, q1, q2, nphi_all=n_lo - 8)
+    assert np.max(np.abs(bad - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
 def test_five_step_resample_plane_wave():
     """Section 3.4: a plane wave e^{i ka s.d} with small |d| is band-limited well below both
     grids, so the five steps reproduce its samples on the other quadrature."""
