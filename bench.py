@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="also run 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the autograd run (2^18 sphere points, kappa 88, loss sum |phi - phi_t|^2)")
     return ap.parse_args()
 
 
@@ -222,6 +224,52 @@ def main():
         del pl
         torch.cuda.empty_cache()
 
+    grad = None
+    if not args.no_grad:
+        # forward + backward of loss = sum |phi - phi_t|^2 through the differentiable matvec;
+        # backward = one adjoint matvec plus one two-RHS field-gradient call
+        ng, kg = 1 << 18, 88.0
+        xg = wl.sphere_points(ng, seed=0)
+        qg = wl.complex_normal(ng, seed=1)
+        phit = wl.complex_normal(ng, seed=3)
+        xgt = torch.as_tensor(xg, dtype=torch.float64, device=dev)
+        qgt = torch.as_tensor(qg, dtype=torch.complex128, device=dev).to(torch.complex64).requires_grad_(True)
+        xgr = xgt.clone().requires_grad_(True)
+        ptt = torch.as_tensor(phit, dtype=torch.complex128, device=dev).to(torch.complex64)
+        pg = ff.Plan(xgt, kg, args.eps, precision="fp32", max_rhs=2)
+
+        def fwd_bwd():
+            xgr.grad = None
+            qgt.grad = None
+            phi = ff.apply(pg, xgr, qgt)
+            (phi - ptt).abs().pow(2).sum().backward()
+
+        msg = timed(fwd_bwd, max(3, args.steps // 2), 1)
+        msf = timed(lambda: pg.matvec(qgt.detach()), max(3, args.steps // 2), 1)
+        grad = {"n": ng, "kappa": kg, "ms_fwd_bwd": msg, "ms_matvec": msf,
+                "value": ng / (msg * 1e-3) / 1e6, "depth": pg.info()["depth"]}
+        if not args.no_cpu:
+            # the backward's parts against the oracle on 256 targets: the forward phi, the adjoint
+            # of a seeded vector g, and the field gradient of q (the full gradient needs phi at
+            # every point; the GPU tests check it at small N)
+            tgg = wl.subset(ng, 256, seed=7)
+            gv = wl.complex_normal(ng, seed=4)
+            gvt = torch.as_tensor(gv, dtype=torch.complex128, device=dev).to(torch.complex64)
+            qd = qgt.detach()
+            phig = pg.matvec(qd).cpu().numpy()[tgg]
+            adj = pg.adjoint(gvt).cpu().numpy()[tgg]
+            fld = pg.field_gradient(qd).cpu().numpy()[tgg]
+            r_phi = direct.matvec(xg, qg, kg, targets=tgg)
+            r_adj = np.conj(direct.matvec(xg, np.conj(gv), kg, targets=tgg))
+            r_fld = direct.gradient(xg, qg, kg, targets=tgg)
+            rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            grad["rel_err_phi"] = rel(phig, r_phi)
+            grad["rel_err_adjoint"] = rel(adj, r_adj)
+            grad["rel_err_field_gradient"] = rel(fld, r_fld)
+        log("autograd: %s" % grad)
+        del pg
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         del plan
@@ -266,6 +314,7 @@ def main():
         "fp64": fp64,
         "batched": batched,
         "large": large,
+        "autograd": grad,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -27,10 +27,12 @@ template <class C> __device__ inline C cz() { C c; c.x = 0; c.y = 0; return c; }
 template <class C, class R> __device__ inline C cmk(R x, R y) { C c; c.x = x; c.y = y; return c; }
 
 // acc += a * b
+// acc += a b with explicit fused operations, so that the rounding does not depend on how the
+// compiler schedules the surrounding loop (batched and single right-hand sides agree bit for bit)
 template <class C> __device__ inline void cmac(C& acc, C a, C b)
 {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 
 template <class C> __device__ inline C cmul(C a, C b)
@@ -186,19 +188,38 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
     __syncthreads();
     if (k >= K) return;
     const int64_t plane = nb * (int64_t)K;
-    const C* Mk = M + k;
+    const C* Mk = M + (int64_t)r0 * plane + k;
     const C* Tk = T + k;
+    const int nr = min(RB, nrhs - r0);
     C acc[RB];
     for (int q = 0; q < RB; ++q) acc[q] = cz<C>();
-    for (int e = 0; e < ne; ++e) {
-        const C t = Tk[(int64_t)s_tix[e] * K];
-        const C* m = Mk + (int64_t)s_src[e] * K;
+    // entries in batches of U: all loads of a batch are issued before the first product, so a
+    // wave keeps U (T, M) pairs in flight instead of one
+    constexpr int U = RB == 1 ? 8 : 4;
+    int e = 0;
+    for (; e + U <= ne; e += U) {
+        C t[U], m[U][RB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            t[u] = Tk[(uint64_t)(uint32_t)s_tix[e + u] * (uint32_t)K];
+            const C* mp = Mk + (uint64_t)(uint32_t)s_src[e + u] * (uint32_t)K;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) m[u][q] = (q < nr) ? mp[(int64_t)q * plane] : cz<C>();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < RB; ++q) cmac(acc[q], m[u][q], t[u]);
+    }
+    for (; e < ne; ++e) {
+        const C t = Tk[(uint64_t)(uint32_t)s_tix[e] * (uint32_t)K];
+        const C* mp = Mk + (uint64_t)(uint32_t)s_src[e] * (uint32_t)K;
 #pragma unroll
         for (int q = 0; q < RB; ++q)
-            if (r0 + q < nrhs) cmac(acc[q], m[(int64_t)(r0 + q) * plane], t);
+            if (q < nr) cmac(acc[q], mp[(int64_t)q * plane], t);
     }
     for (int q = 0; q < RB; ++q)
-        if (r0 + q < nrhs) out[(int64_t)(r0 + q) * plane + b * K + k] = acc[q];
+        if (q < nr) out[(int64_t)(r0 + q) * plane + b * K + k] = acc[q];
 }
 
 // ------------------------------------------------------------------------------------------
