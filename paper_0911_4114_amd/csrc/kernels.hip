@@ -87,6 +87,18 @@ __device__ inline unsigned xcd_block(unsigned b, unsigned nblocks)
     return x * per + min(x, rem) + i;
 }
 
+// Kernels that give each wave its own box run kWpb waves per block: blocks of one wave are few
+// per CU and leave the SIMDs short of waves to hide latency with. The waves of a block then work
+// on different boxes and hand LDS data between their own lanes only: a wave executes its LDS
+// operations in order, so a fence at wavefront scope (which also stops the compiler moving memory
+// operations across it) is the whole synchronisation.
+constexpr int kWpb = 4;
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ------------------------------------------------------------------------------------------
 // permutation with optional conjugation
 // ------------------------------------------------------------------------------------------
@@ -225,14 +237,14 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
 // ------------------------------------------------------------------------------------------
 // L2P (far part of eqn. FMM_FinalStep): phi_i += sum_k w_k L_b(s_k) e^{i kappa s_k.(c_b - x_i)};
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
-// One wave per leaf box, one lane per target point; w_k L_b(s_k) and s_k are staged in LDS in
-// chunks. The sum over k is blocked: plain sums of 16 terms, combined with TwoSum, which keeps
+// One wave per leaf box (four per block), one lane per target point; w_k L_b(s_k) and s_k are
+// staged in the wave's own LDS in chunks. The sum over k is blocked: plain sums of 16 terms, combined with TwoSum, which keeps
 // the FP32 accumulation error of the large cancelling terms near the size of the result.
 // ------------------------------------------------------------------------------------------
-constexpr int kL2PChunk = 512;
+constexpr int kL2PChunk = 256;
 
 template <class R, class C, bool GRAD>
-__global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__ dirs,
+__global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __restrict__ dirs,
                                                     const R* __restrict__ w, R kfac, R kappa,
                                                     const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ count,
@@ -240,11 +252,16 @@ __global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__
                                                     C* __restrict__ out, int64_t n, int64_t nb)
 {
     constexpr int NC = GRAD ? 3 : 1;
-    __shared__ R sx[kL2PChunk], sy[kL2PChunk], sz[kL2PChunk];
-    __shared__ C swl[kL2PChunk];
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    __shared__ R sxa[kWpb][kL2PChunk], sya[kWpb][kL2PChunk], sza[kWpb][kL2PChunk];
+    __shared__ C swla[kWpb][kL2PChunk];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
+    if (b >= nb) return;
+    R* sx = sxa[wv];
+    R* sy = sya[wv];
+    R* sz = sza[wv];
+    C* swl = swla[wv];
     const int64_t r = blockIdx.y;
-    const int lane = threadIdx.x;
     const int s0 = start[b], cnt = count[b];
     const C* Lb = L + (r * nb + b) * K;
     for (int t0 = 0; t0 < cnt; t0 += kWave) {
@@ -260,7 +277,7 @@ __global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__
         for (int a = 0; a < NC; ++a) sre[a] = sim[a] = ere[a] = eim[a] = 0;
         for (int k0 = 0; k0 < K; k0 += kL2PChunk) {
             const int nk = min(kL2PChunk, K - k0);
-            __syncthreads();
+            wave_lds_sync();
             for (int k = lane; k < nk; k += kWave) {
                 const int kk = k0 + k;
                 sx[k] = dirs[3 * kk];
@@ -269,7 +286,7 @@ __global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__
                 const C lv = Lb[kk];
                 swl[k] = cmk<C>(w[kk] * lv.x, w[kk] * lv.y);
             }
-            __syncthreads();
+            wave_lds_sync();
             for (int kb = 0; kb < nk; kb += 16) {
                 const int ke = min(kb + 16, nk);
                 R pre[NC], pim[NC];
@@ -310,26 +327,31 @@ __global__ __launch_bounds__(kWave) void l2p_kernel(int K, const R* __restrict__
 // ------------------------------------------------------------------------------------------
 // P2P (near part of eqn. FMM_FinalStep): phi_i += sum_{j in N(b), j != i, R > 0} e^{i kappa R}/R q_j;
 // with GRAD: sum G'(R) (x_i - x_j)/R q_j, G'(R) = e^{i kappa R}(i kappa R - 1)/R^2.
-// One wave per leaf box, lanes = targets, source points staged in LDS 64 at a time.
+// One wave per leaf box (four per block), lanes = targets (g lanes per target when the box has few
+// points), source points staged in the wave's own LDS 64 at a time.
 // R and kappa R in FP64; in the FP32 path kappa R is reduced modulo 2 pi in FP64 and the
 // sine/cosine, 1/R and the sums are FP32.
 // ------------------------------------------------------------------------------------------
 template <class R, class C, bool GRAD>
-__global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ xs,
+__global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restrict__ xs,
                                                     const C* __restrict__ q,
                                                     const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ count,
                                                     const int32_t* __restrict__ nb_ptr,
                                                     const int32_t* __restrict__ nb_src, double kappa,
-                                                    C* __restrict__ out, int64_t n)
+                                                    C* __restrict__ out, int64_t n, int64_t nleaf)
 {
     constexpr int NC = GRAD ? 3 : 1;
-    __shared__ double sx[kWave], sy[kWave], sz[kWave];
-    __shared__ C sq[kWave];
-    __shared__ C part[NC][kWave];
-    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    __shared__ double4 spa[kWpb][kWave];   // staged sources: x, y, z (w unused)
+    __shared__ C sqa[kWpb][kWave];
+    __shared__ C parta[kWpb][NC][kWave];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
+    if (b >= nleaf) return;
+    double4* sp = spa[wv];
+    C* sq = sqa[wv];
+    C (*part)[kWave] = parta[wv];
     const int64_t r = blockIdx.y;
-    const int lane = threadIdx.x;
     const int tb = start[b], tc = count[b];
     const double kappa_rev = kappa / kTwoPi;
     for (int t0 = 0; t0 < tc; t0 += kWave) {
@@ -347,38 +369,39 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
             const int sb = start[c], sc = count[c];
             for (int s0 = 0; s0 < sc; s0 += kWave) {
                 const int ns = min(kWave, sc - s0);
-                __syncthreads();
+                wave_lds_sync();
                 if (lane < ns) {
                     const int64_t j = sb + s0 + lane;
-                    sx[lane] = xs[3 * j];
-                    sy[lane] = xs[3 * j + 1];
-                    sz[lane] = xs[3 * j + 2];
+                    sp[lane] = make_double4(xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], 0.0);
                     sq[lane] = q[r * n + j];
                 }
-                __syncthreads();
+                wave_lds_sync();
                 if (!valid) continue;
                 for (int t = sub; t < ns; t += g) {
-                    const int64_t j = sb + s0 + t;
-                    const double dx = xi - sx[t], dy = yi - sy[t], dz = zi - sz[t];
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const bool ok = (j != i) && (r2 > 0.0);
+                    const double4 pj = sp[t];
+                    const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    // R = 0 exactly for the target itself (and for coincident points): excluded
+                    const bool ok = r2 > 0.0;
+                    const double r2s = ok ? r2 : 1.0;
                     R c, s, inv;
                     double rr;
                     if constexpr (sizeof(R) == 4) {
-                        // 1/R from the hardware reciprocal square root of the FP32-rounded R^2,
-                        // refined by one Newton step in FP64 (relative error ~1e-14), so R and the
-                        // phase kappa R / 2 pi stay FP64-accurate; the phase is reduced modulo 1
-                        // in FP64 before the FP32 sine/cosine.
-                        const double r2s = ok ? r2 : 1.0;
-                        const double y0 = (double)__builtin_amdgcn_rsqf((float)r2s);
-                        const double y1 = y0 * (1.5 - 0.5 * r2s * y0 * y0);
-                        rr = r2s * y1;
+                        // y0 = hardware reciprocal square root of the FP32-rounded R^2; one Newton
+                        // step in FP64 written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so
+                        // R and the phase kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the
+                        // phase is reduced modulo 1 in FP64 before the FP32 sine/cosine, and
+                        // 1/R = y0 (1 + e) needs FP32 only.
+                        const float y0f = __builtin_amdgcn_rsqf((float)r2s);
+                        const double y0 = (double)y0f;
+                        const double u = r2s * y0;
+                        const double eh = fma(-0.5, u * y0, 0.5);
+                        rr = fma(u, eh, u);
                         double rev = rr * kappa_rev;
                         rev -= floor(rev);
                         cis((float)rev, c, s);
-                        inv = ok ? (float)y1 : 0.0f;
+                        inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
                     } else {
-                        const double r2s = ok ? r2 : 1.0;
                         rr = sqrt(r2s);
                         cis(kappa * rr, c, s);
                         inv = ok ? 1.0 / rr : 0.0;
@@ -402,7 +425,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
         }
         // combine the g partial sums of every target
         for (int a = 0; a < NC; ++a) part[a][lane] = acc[a];
-        __syncthreads();
+        wave_lds_sync();
         if (valid && sub == 0)
             for (int a = 0; a < NC; ++a) {
                 C sum = part[a][lane];
@@ -414,7 +437,7 @@ __global__ __launch_bounds__(kWave) void p2p_kernel(const double* __restrict__ x
                 o.x += sum.x;
                 o.y += sum.y;
             }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -491,12 +514,12 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         // L2P
         StageScope sc(p, FFMM_PROF_L2P, s);
         if (gradient)
-            hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3((unsigned)leaf.n, nrhs), dim3(kWave), 0, s,
+            hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
                                leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
                                p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
                                phis, n, leaf.n);
         else
-            hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3((unsigned)leaf.n, nrhs), dim3(kWave), 0, s,
+            hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
                                leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
                                p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
                                phis, n, leaf.n);
@@ -506,13 +529,13 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         StageScope sc(p, FFMM_PROF_P2P, s);
         const int64_t nl = p->lev[L].n;
         if (gradient)
-            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3((unsigned)nl, nrhs), dim3(kWave), 0, s,
+            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
                                p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phis, n);
+                               phis, n, (int64_t)nl);
         else
-            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3((unsigned)nl, nrhs), dim3(kWave), 0, s,
+            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
                                p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phis, n);
+                               phis, n, (int64_t)nl);
         FFMM_LAUNCH_CHECK();
     }
     {
