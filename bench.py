@@ -89,6 +89,30 @@ def stage_work(info, stage):
     return "hbm", 0.0, "GB"
 
 
+# HBM traffic of the dominant kernel: FETCH_SIZE and WRITE_SIZE per dispatch from rocprofv3 --pmc,
+# scaled by the same counters on a plain device copy (profiles/, written by
+# ``python -m paper_0911_4114_amd.profiling traffic``); reported only while the kernel's source file
+# is the one the counters were taken on, else null.
+TRAFFIC_FILES = {
+    "p2p": ("profiles/traffic_p2p_fp32_sphere1M_k177.txt", "p2p_kernel<float, float2, false>"),
+}
+
+
+def measured_traffic(stage, args):
+    here = os.path.dirname(os.path.abspath(__file__))
+    if stage not in TRAFFIC_FILES or args.n != 1 << 20 or args.kappa != 177.0 or args.eps != 1e-4:
+        return None
+    rel, kernel = TRAFFIC_FILES[stage]
+    path = os.path.join(here, rel)
+    if not os.path.exists(path):
+        return None
+    from paper_0911_4114_amd.profiling import file_sha256, read_traffic
+    t = read_traffic(path)
+    if t.get("kernel") != kernel or t.get("source_sha256") != file_sha256(os.path.join(here, t["source"])):
+        return None
+    return float(t["hbm_bytes_per_dispatch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -161,6 +185,7 @@ def main():
                 "frac": achieved / peak, "traffic": None}
     roof["stage"] = dom
     roof["launch_ms"] = per_launch_ms
+    roof["traffic"] = measured_traffic(dom, args)
 
     # accuracy against the oracle's direct sum on a subset of targets (host FP64)
     out = plan.matvec(q32).cpu().numpy().astype(np.complex128)

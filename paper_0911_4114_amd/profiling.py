@@ -3,9 +3,16 @@
 ``python -m paper_0911_4114_amd.profiling trace <results.db|kernel_trace.csv> [top]`` prints a
 per-kernel Markdown table (calls, total and average duration).
 ``python -m paper_0911_4114_amd.profiling pmc <counter_collection.csv> <kernel substring> <counter>``
-prints the mean of a counter over the dispatches of the matching kernels."""
+prints the mean of a counter over the dispatches of the matching kernels.
+``python -m paper_0911_4114_amd.profiling traffic --kernel NAME --fetch CSV --write CSV
+--copy-fetch CSV --copy-write CSV --copy-bytes B --source FILE`` prints the HBM-traffic summary
+of one kernel (its largest launches): FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what
+the same counter reads for a plain device copy of B bytes, plus the SHA-256 of the kernel's source
+file, so that a reader can tell whether the figures still describe the code."""
+import argparse
 import csv
 import collections
+import hashlib
 import sqlite3
 import sys
 
@@ -43,6 +50,61 @@ def pmc_mean(path, kernel, counter):
     return sum(vals.values()) / max(len(vals), 1), len(vals)
 
 
+def counter_per_dispatch(path, counter, kernel=None, largest=True):
+    """Mean counter value (summed over its instances) per dispatch of the kernel whose short name
+    equals ``kernel`` (any kernel if None), over the dispatches with the largest grid."""
+    vals, grid = collections.defaultdict(float), {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        if kernel is not None and short_name(r["Kernel_Name"]) != kernel:
+            continue
+        vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        grid[r["Dispatch_Id"]] = int(r["Grid_Size"])
+    if not vals:
+        raise SystemExit("no %s rows for %s in %s" % (counter, kernel, path))
+    g = max(grid.values()) if largest else None
+    sel = [v for d, v in vals.items() if not largest or grid[d] == g]
+    return sum(sel) / len(sel), len(sel), g
+
+
+def file_sha256(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def traffic_summary(a):
+    cf, _, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
+    cw, _, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
+    f, nf, gf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
+    w, nw, gw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    fs, ws = a.copy_bytes / (cf * 1024.0), a.copy_bytes / (cw * 1024.0)
+    lines = [
+        "kernel: %s" % a.kernel,
+        "grid_size: %d" % gf,
+        "source: %s" % a.source,
+        "source_sha256: %s" % file_sha256(a.source),
+        "fetch_kib_per_dispatch: %.1f (%d dispatches)" % (f, nf),
+        "write_kib_per_dispatch: %.1f (%d dispatches)" % (w, nw),
+        "copy_bytes: %d" % a.copy_bytes,
+        "copy_fetch_kib: %.1f" % cf,
+        "copy_write_kib: %.1f" % cw,
+        "fetch_scale: %.4f" % fs,
+        "write_scale: %.4f" % ws,
+        "hbm_bytes_per_dispatch: %.0f" % (1024.0 * (f * fs + w * ws)),
+    ]
+    return "\n".join(lines)
+
+
+def read_traffic(path):
+    """key -> value (first token) of a summary written by ``traffic``."""
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip().split(" (")[0]
+    return out
+
+
 def main(path, top=25):
     rows = trace_rows(path, top)
     print("| kernel | calls | total (us) | average (us) | % |")
@@ -52,7 +114,19 @@ def main(path, top=25):
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "trace":
+    if sys.argv[1] == "traffic":
+        ap = argparse.ArgumentParser(prog="profiling traffic")
+        ap.add_argument("--kernel", required=True)
+        ap.add_argument("--fetch", required=True)
+        ap.add_argument("--write", required=True)
+        ap.add_argument("--copy-fetch", required=True)
+        ap.add_argument("--copy-write", required=True)
+        ap.add_argument("--copy-bytes", type=int, required=True)
+        ap.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer",
+                        help="short name of the copy kernel (a device-to-device tensor copy)")
+        ap.add_argument("--source", required=True)
+        print(traffic_summary(ap.parse_args(sys.argv[2:])))
+    elif sys.argv[1] == "trace":
         main(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25)
     elif sys.argv[1] == "pmc":
         m, cnt = pmc_mean(sys.argv[2], sys.argv[3], sys.argv[4])
