@@ -223,7 +223,9 @@ ffmm_status ffmm_plan_get_nphi(const ffmm_plan* plan, int32_t l, int32_t* nphi);
 /*
  * Band-limited modified transfer function T^{s,LL} of level l for offset code `code`
  * (0..342, not an inner code) sampled on the level quadrature: host complex128[K_l]
- * (converted to FP64 for an FP32 plan).
+ * (converted to FP64 for an FP32 plan). The plan stores T for the 34 transfer vectors that are
+ * distinct up to the quadrature's symmetries (Section 3.2, Fig. SemiOctant); this call rebuilds
+ * the requested one by the direction permutation of its symmetry.
  */
 ffmm_status ffmm_plan_get_transfer(const ffmm_plan* plan, int32_t l, int32_t code, double* out);
 

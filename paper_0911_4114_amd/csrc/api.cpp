@@ -129,6 +129,19 @@ static void allocate_workspaces(ffmm_plan* p)
     p->scratch2 = p->arena.alloc(p->scratch2_bytes);
     p->qs = p->arena.alloc(cs * (size_t)mr * p->n);
     p->phis = p->arena.alloc(cs * (size_t)mr * p->n * 3);
+    p->phin = p->arena.alloc(cs * (size_t)mr * p->n * 3);
+    FFMM_HIP(hipStreamCreateWithFlags(&p->near_stream, hipStreamNonBlocking));
+    FFMM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    FFMM_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+}
+
+static void release_streams(ffmm_plan* p)
+{
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->near_stream) (void)hipStreamDestroy(p->near_stream);
+    p->ev_fork = p->ev_join = nullptr;
+    p->near_stream = nullptr;
 }
 
 }  // namespace ffmm
@@ -209,6 +222,7 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
     });
     if (st != FFMM_OK && p) {
         (void)hipDeviceSynchronize();
+        release_streams(p);
         p->arena.release();
         delete p;
     }
@@ -318,6 +332,7 @@ ffmm_status ffmm_plan_destroy(ffmm_plan* p)
         if (!p) return;
         (void)hipDeviceSynchronize();
         drain_events(p, false);
+        release_streams(p);
         p->arena.release();
         delete p;
     });
@@ -426,12 +441,21 @@ ffmm_status ffmm_plan_get_transfer(const ffmm_plan* p, int32_t l, int32_t code, 
         if (!p || !out) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
         if (l < 2 || l > p->depth) fail(FFMM_ERR_INVALID_ARG, "level out of range");
         if (code < 0 || code >= kNumCodes) fail(FFMM_ERR_INVALID_ARG, "code out of range");
-        int32_t map[kNumCodes];
-        offset_code_map(map);
-        if (map[code] < 0) fail(FFMM_ERR_INVALID_ARG, "inner offset code has no transfer function");
+        int rep, g;
+        if (!offset_symmetry(code, &rep, &g))
+            fail(FFMM_ERR_INVALID_ARG, "inner offset code has no transfer function");
+        // T_{g rep}(s_k) = T_rep(s_{tperm[g][k]}): gather the representative's table
         const LevelData& L = p->lev[l];
-        const char* base = (const char*)L.transfer + csize(p) * (size_t)map[code] * L.K;
-        copy_complex_to_f64(p, base, L.K, out);
+        const char* base = (const char*)L.transfer + csize(p) * (size_t)rep * L.K;
+        std::vector<double> t(2 * (size_t)L.K);
+        copy_complex_to_f64(p, base, L.K, t.data());
+        std::vector<int32_t> perm(L.K);
+        FFMM_HIP(hipMemcpy(perm.data(), L.tperm + (size_t)g * L.K, sizeof(int32_t) * L.K,
+                           hipMemcpyDeviceToHost));
+        for (int k = 0; k < L.K; ++k) {
+            out[2 * k] = t[2 * (size_t)perm[k]];
+            out[2 * k + 1] = t[2 * (size_t)perm[k] + 1];
+        }
     });
 }
 

@@ -31,6 +31,8 @@ struct Error {
 constexpr int kMaxDepth = 21;        // bits per axis of the Morton keys
 constexpr int kNumOffsets = 316;     // transfer vectors per level (Section 3.2)
 constexpr int kNumCodes = 343;       // 7^3 offset codes, inner 3^3 unused
+constexpr int kNumReps = 34;         // transfer vectors up to the quadrature's symmetries (Fig. SemiOctant)
+constexpr int kNumSym = 16;          // those symmetries: x <-> y swap, then reflections of x, y, z
 
 // Device allocations owned by a plan.
 struct DeviceArena {
@@ -58,7 +60,7 @@ struct LevelData {
     int32_t* il_ptr = nullptr;      // [n+1]
     int32_t* il_src = nullptr;      // [n_il]
     int32_t* il_code = nullptr;     // [n_il] offset code 0..342
-    int32_t* il_tix = nullptr;      // [n_il] transfer table row 0..315
+    int32_t* il_tix = nullptr;      // [n_il] 16 rep + g: representative table and symmetry (tsym)
     // quadrature (levels >= 2)
     LevelParams par;
     int K = 0;
@@ -68,7 +70,8 @@ struct LevelData {
     int32_t* d_nphi = nullptr;
     void* dirs = nullptr;           // [K][3] real
     void* weights = nullptr;        // [K] real (leaf level)
-    void* transfer = nullptr;       // [316][K] complex
+    void* transfer = nullptr;       // [34][K] complex: T of the representative transfer vectors
+    int32_t* tperm = nullptr;       // [16][K]: T_{g rep}(s_k) = T_rep(s_{tperm[g][k]})
     void* trans = nullptr;          // [8][K] complex: e^{i kappa s.(oct - 1/2) a_{l+1}} (l < L)
     void* sigM = nullptr;           // [max_rhs][n][K] complex
     void* sigL = nullptr;           // [max_rhs][n][K] complex
@@ -121,7 +124,12 @@ struct ffmm_plan {
     std::vector<ffmm::Resampler> up;        // up[l]: level l -> l-1 (l = 3..L)
     std::vector<ffmm::Resampler> down;      // down[l]: level l -> l+1 (l = 2..L-1)
     void* qs = nullptr;             // [max_rhs][n] complex, sorted charges
-    void* phis = nullptr;           // [max_rhs][n] complex (or [max_rhs][n][3] for gradients)
+    void* phis = nullptr;           // far field (L2P): [max_rhs][n] complex ([..][3] for gradients)
+    void* phin = nullptr;           // near field (P2P), same shape
+    // P2P runs on its own stream, forked after the charge gather and joined before the scatter,
+    // so that it overlaps the far-field stages (default priority, non-blocking)
+    hipStream_t near_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void* scratch1 = nullptr;       // resample workspaces
     void* scratch2 = nullptr;
     size_t scratch1_bytes = 0, scratch2_bytes = 0;
@@ -162,6 +170,14 @@ void make_parent_tiles(const std::vector<int32_t>& child_count, std::vector<int3
 
 // map offset code (0..342) -> transfer table row (0..315), -1 for the inner 27 codes
 void offset_code_map(int32_t* map);
+// Symmetry decomposition of a transfer vector d (|d_a| <= 3, max >= 2): d = g(rep) with rep =
+// (dx >= dy >= 0, dz >= 0) one of 34 representatives and g = swap x <-> y (bit 0) followed by the
+// reflections of x (bit 1), y (bit 2), z (bit 3). Returns false for the 27 inner codes.
+bool offset_symmetry(int code, int* rep, int* g);
+void rep_offset(int rep, int d[3]);
+// Index of the direction g^{-1}(s_k) on a level quadrature (rows 0..N_theta/2, row lengths
+// N_phi(theta_n), row n and N_theta/2 - n of equal length).
+int sym_direction(int g, int n, int m, int ntheta, int nphi_n, const std::vector<int>& row_off);
 
 // exclusive prefix sum of n int32 values; returns the total (synchronises the stream)
 int64_t exclusive_scan(DeviceArena& tmp, const int32_t* in, int32_t* out, int64_t n, hipStream_t s);

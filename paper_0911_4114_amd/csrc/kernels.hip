@@ -115,14 +115,21 @@ __global__ void gather_q(const C* __restrict__ q, const int64_t* __restrict__ pe
 }
 
 template <class C>
-__global__ void scatter_out(const C* __restrict__ phis, const int64_t* __restrict__ perm, int64_t n,
-                            int width, int conj, C* __restrict__ out)
+__global__ void scatter_out(const C* __restrict__ far, const C* __restrict__ near,
+                            const int64_t* __restrict__ perm, int64_t n, int width, int conj,
+                            C* __restrict__ out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t r = blockIdx.y;
     for (int a = 0; a < width; ++a) {
-        C v = phis[(r * n + i) * width + a];
+        const int64_t k = (r * n + i) * width + a;
+        C v = cz<C>();
+        if (far) v = far[k];
+        if (near) {
+            v.x += near[k].x;
+            v.y += near[k].y;
+        }
         if (conj) v.y = -v.y;
         out[(r * n + perm[i]) * width + a] = v;
     }
@@ -177,13 +184,16 @@ __global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* _
 // ------------------------------------------------------------------------------------------
 // M2L (Transfer pass, Section 2): I_b(s_k) = sum_{e in I(b)} M_src(e)(s_k) T_off(e)(s_k).
 // Block: one target box, 256 directions; the interaction list is staged in LDS; each T value read
-// serves RB right-hand sides.
+// serves RB right-hand sides. T is stored for the 34 representative transfer vectors only: the
+// entry's vector is g(rep) for a symmetry g of the quadrature, and T_{g rep}(s_k) =
+// T_rep(s_{tperm[g][k]}); each thread keeps its 16 permuted directions in registers.
 // ------------------------------------------------------------------------------------------
 template <class C, int RB>
 __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
                                                   const int32_t* __restrict__ il_ptr,
                                                   const int32_t* __restrict__ il_src,
                                                   const int32_t* __restrict__ il_tix,
+                                                  const int32_t* __restrict__ tperm,
                                                   const C* __restrict__ T, const C* __restrict__ M,
                                                   C* __restrict__ out, int64_t nb, int nrhs)
 {
@@ -201,7 +211,14 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
     if (k >= K) return;
     const int64_t plane = nb * (int64_t)K;
     const C* Mk = M + (int64_t)r0 * plane + k;
-    const C* Tk = T + k;
+    int kp[kNumSym];
+#pragma unroll
+    for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[g * K + k];
+    // T value of entry e (its packed index is uniform across the block)
+    auto tval = [&](int e) {
+        const int tx = __builtin_amdgcn_readfirstlane(s_tix[e]);
+        return T[(uint64_t)(uint32_t)(tx >> 4) * (uint32_t)K + kp[tx & (kNumSym - 1)]];
+    };
     const int nr = min(RB, nrhs - r0);
     C acc[RB];
     for (int q = 0; q < RB; ++q) acc[q] = cz<C>();
@@ -213,7 +230,7 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
         C t[U], m[U][RB];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            t[u] = Tk[(uint64_t)(uint32_t)s_tix[e + u] * (uint32_t)K];
+            t[u] = tval(e + u);
             const C* mp = Mk + (uint64_t)(uint32_t)s_src[e + u] * (uint32_t)K;
 #pragma unroll
             for (int q = 0; q < RB; ++q) m[u][q] = (q < nr) ? mp[(int64_t)q * plane] : cz<C>();
@@ -224,7 +241,7 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
             for (int q = 0; q < RB; ++q) cmac(acc[q], m[u][q], t[u]);
     }
     for (; e < ne; ++e) {
-        const C t = Tk[(uint64_t)(uint32_t)s_tix[e] * (uint32_t)K];
+        const C t = tval(e);
         const C* mp = Mk + (uint64_t)(uint32_t)s_src[e] * (uint32_t)K;
 #pragma unroll
         for (int q = 0; q < RB; ++q)
@@ -315,12 +332,8 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __res
                 }
             }
         }
-        if (valid)
-            for (int a = 0; a < NC; ++a) {
-                C& o = out[(r * n + i) * NC + a];
-                o.x += sre[a] + ere[a];
-                o.y += sim[a] + eim[a];
-            }
+        if (valid)   // every point lies in one leaf: a plain store
+            for (int a = 0; a < NC; ++a) out[(r * n + i) * NC + a] = cmk<C>(sre[a] + ere[a], sim[a] + eim[a]);
     }
 }
 
@@ -433,9 +446,7 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
                     sum.x += part[a][lane + u].x;
                     sum.y += part[a][lane + u].y;
                 }
-                C& o = out[(r * n + i) * NC + a];
-                o.x += sum.x;
-                o.y += sum.y;
+                out[(r * n + i) * NC + a] = sum;   // every point lies in one leaf: a plain store
             }
         wave_lds_sync();
     }
@@ -464,6 +475,7 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
     const int width = gradient ? 3 : 1;
     C* qs = (C*)p->qs;
     C* phis = (C*)p->phis;
+    C* phin = (C*)p->phin;
     const R kfac = phase_scale<R>(p->kappa);
 
     {
@@ -471,7 +483,23 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         hipLaunchKernelGGL(gather_q<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)qv,
                            p->perm, n, conj_io ? 1 : 0, qs);
         FFMM_LAUNCH_CHECK();
-        FFMM_HIP(hipMemsetAsync(phis, 0, sizeof(C) * (size_t)nrhs * n * width, s));
+    }
+    // P2P needs only the gathered charges: fork it onto the plan's near-field stream
+    if (stages & FFMM_STAGE_NEAR) {
+        hipStream_t sn = p->near_stream;
+        FFMM_HIP(hipEventRecord(p->ev_fork, s));
+        FFMM_HIP(hipStreamWaitEvent(sn, p->ev_fork, 0));
+        StageScope sc(p, FFMM_PROF_P2P, sn);
+        const int64_t nl = p->lev[L].n;
+        if (gradient)
+            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, sn,
+                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
+                               phin, n, (int64_t)nl);
+        else
+            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, sn,
+                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
+                               phin, n, (int64_t)nl);
+        FFMM_LAUNCH_CHECK();
     }
 
     if (stages & FFMM_STAGE_FAR) {
@@ -498,11 +526,11 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
             const unsigned gx = (unsigned)(Lv.n * kch);
             if (nrhs >= 4)
                 hipLaunchKernelGGL((m2l_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), dim3(256), 0, s,
-                                   Lv.K, kch, Lv.il_ptr, Lv.il_src, Lv.il_tix, (const C*)Lv.transfer,
-                                   (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                                   Lv.K, kch, Lv.il_ptr, Lv.il_src, Lv.il_tix, Lv.tperm,
+                                   (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
             else
                 hipLaunchKernelGGL((m2l_kernel<C, 1>), dim3(gx, nrhs), dim3(256), 0, s, Lv.K, kch,
-                                   Lv.il_ptr, Lv.il_src, Lv.il_tix, (const C*)Lv.transfer,
+                                   Lv.il_ptr, Lv.il_src, Lv.il_tix, Lv.tperm, (const C*)Lv.transfer,
                                    (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
             FFMM_LAUNCH_CHECK();
         }
@@ -526,22 +554,16 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         FFMM_LAUNCH_CHECK();
     }
     if (stages & FFMM_STAGE_NEAR) {
-        StageScope sc(p, FFMM_PROF_P2P, s);
-        const int64_t nl = p->lev[L].n;
-        if (gradient)
-            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phis, n, (int64_t)nl);
-        else
-            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phis, n, (int64_t)nl);
-        FFMM_LAUNCH_CHECK();
+        // join: the scatter waits for P2P (and the next call's gather for this P2P's reads of qs)
+        FFMM_HIP(hipEventRecord(p->ev_join, p->near_stream));
+        FFMM_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
     }
     {
         StageScope sc(p, FFMM_PROF_SCATTER, s);
-        hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)phis,
-                           p->perm, n, width, conj_io ? 1 : 0, (C*)outv);
+        hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s,
+                           (stages & FFMM_STAGE_FAR) ? (const C*)phis : (const C*)nullptr,
+                           (stages & FFMM_STAGE_NEAR) ? (const C*)phin : (const C*)nullptr, p->perm, n,
+                           width, conj_io ? 1 : 0, (C*)outv);
         FFMM_LAUNCH_CHECK();
     }
 }

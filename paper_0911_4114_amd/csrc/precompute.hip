@@ -245,16 +245,14 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
         for (int n = 0; n < rows; ++n)
             for (int k = L.row_off[n]; k < L.row_off[n + 1]; ++k) row_of_k[k] = n;
         int32_t* d_rok = upload_int(tmp, row_of_k, s);
-        // offsets, coefficient sets per offset
-        int32_t map[kNumCodes];
-        offset_code_map(map);
-        std::vector<double> r0hat(3 * kNumOffsets);
-        std::vector<cd> cn((size_t)kNumOffsets * (ell + 1));
+        // the 34 representative transfer vectors (the other 282 are their images under the
+        // quadrature's symmetries, read through tperm), coefficient sets per vector
+        std::vector<double> r0hat(3 * kNumReps);
+        std::vector<cd> cn((size_t)kNumReps * (ell + 1));
         std::vector<double> jn(ell + 1), yn(ell + 1);
-        for (int c = 0; c < kNumCodes; ++c) {
-            int o = map[c];
-            if (o < 0) continue;
-            int d[3] = {c % 7 - 3, (c / 7) % 7 - 3, c / 49 - 3};
+        for (int o = 0; o < kNumReps; ++o) {
+            int d[3];
+            rep_offset(o, d);
             double len = std::sqrt((double)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
             for (int a = 0; a < 3; ++a) r0hat[3 * o + a] = d[a] / len;
             const double r0 = len * L.a;   // physical |r0|
@@ -274,17 +272,17 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
         FFMM_HIP(hipMemcpy(dr0, r0hat.data(), sizeof(double) * r0hat.size(), hipMemcpyHostToDevice));
         // batch the offsets so that the samples stay below ~256 MB
         const size_t per_off = sizeof(double2) * ((size_t)nt * ncols + 2 * (size_t)rows * ncols);
-        int batch = (int)std::max<size_t>(1, std::min<size_t>(kNumOffsets, (256u << 20) / per_off));
+        int batch = (int)std::max<size_t>(1, std::min<size_t>(kNumReps, (256u << 20) / per_off));
         double2* A = tmp.alloc_n<double2>((size_t)batch * nt * ncols);
         double2* TL = tmp.alloc_n<double2>((size_t)batch * rows * ncols);
         double2* Cf = tmp.alloc_n<double2>((size_t)batch * rows * (ncols - 1));
-        double2* T64 = tmp.alloc_n<double2>((size_t)kNumOffsets * K);
+        double2* T64 = tmp.alloc_n<double2>((size_t)kNumReps * K);
         std::vector<cd> tw(ncols);
         for (int t = 0; t < ncols; ++t) tw[t] = std::exp(cd(0.0, -2.0 * kPi * t / ncols));
         double2* dtw = tmp.alloc_n<double2>(ncols);
         FFMM_HIP(hipMemcpy(dtw, tw.data(), sizeof(double2) * ncols, hipMemcpyHostToDevice));
-        for (int o0 = 0; o0 < kNumOffsets; o0 += batch) {
-            const int nb = std::min(batch, kNumOffsets - o0);
+        for (int o0 = 0; o0 < kNumReps; o0 += batch) {
+            const int nb = std::min(batch, kNumReps - o0);
             int64_t tot = (int64_t)nb * nt * ncols;
             hipLaunchKernelGGL(bmtf_sample, dim3(nblk(tot, 256)), dim3(256), 0, s, nb, ell, ncols,
                                dcn + (size_t)o0 * (ell + 1), dr0 + 3 * o0, A);
@@ -302,10 +300,18 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
                                L.d_row_off, L.d_nphi, d_rok, Cf, T64 + (size_t)o0 * K);
             FFMM_LAUNCH_CHECK();
         }
-        const int64_t tot = (int64_t)kNumOffsets * K;
+        const int64_t tot = (int64_t)kNumReps * K;
         L.transfer = p->arena.alloc(sizeof(R) * 2 * tot);
         hipLaunchKernelGGL(to_precision<R>, dim3(nblk(tot, 256)), dim3(256), 0, s, T64, tot, L.transfer);
         FFMM_LAUNCH_CHECK();
+        // tperm[g][k]: direction g^{-1}(s_k), so that T_{g rep}(s_k) = T_rep(s_{tperm[g][k]})
+        std::vector<int> perm((size_t)kNumSym * K);
+        for (int g = 0; g < kNumSym; ++g)
+            for (int n = 0; n < rows; ++n)
+                for (int m = 0; m < L.par.nphi[n]; ++m)
+                    perm[(size_t)g * K + L.row_off[n] + m] =
+                        sym_direction(g, n, m, ntheta, L.par.nphi[n], L.row_off);
+        L.tperm = upload_int(p->arena, perm, s);
         FFMM_HIP(hipStreamSynchronize(s));
     } catch (...) {
         tmp.release();

@@ -435,14 +435,66 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
-// Host map offset code (0..342) -> transfer table row (0..315), -1 for the inner 27 codes.
+void rep_offset(int rep, int d[3])
+{
+    int r = 0;
+    for (int dz = 0; dz <= 3; ++dz)
+        for (int dx = 0; dx <= 3; ++dx)
+            for (int dy = 0; dy <= dx; ++dy) {
+                if (std::max(dx, dz) <= 1) continue;
+                if (r++ == rep) {
+                    d[0] = dx;
+                    d[1] = dy;
+                    d[2] = dz;
+                    return;
+                }
+            }
+    d[0] = d[1] = d[2] = 0;
+}
+
+bool offset_symmetry(int code, int* rep, int* g)
+{
+    const int d[3] = {code % 7 - 3, (code / 7) % 7 - 3, code / 49 - 3};
+    const int ax = std::abs(d[0]), ay = std::abs(d[1]), az = std::abs(d[2]);
+    if (std::max(ax, std::max(ay, az)) <= 1) return false;
+    const int rx = std::max(ax, ay), ry = std::min(ax, ay);
+    int r = 0, found = -1;
+    for (int dz = 0; dz <= 3 && found < 0; ++dz)
+        for (int dx = 0; dx <= 3 && found < 0; ++dx)
+            for (int dy = 0; dy <= dx; ++dy) {
+                if (std::max(dx, dz) <= 1) continue;
+                if (dx == rx && dy == ry && dz == az) {
+                    found = r;
+                    break;
+                }
+                ++r;
+            }
+    *rep = found;
+    *g = (ax < ay ? 1 : 0) | (d[0] < 0 ? 2 : 0) | (d[1] < 0 ? 4 : 0) | (d[2] < 0 ? 8 : 0);
+    return true;
+}
+
+int sym_direction(int g, int n, int m, int ntheta, int nphi_n, const std::vector<int>& row_off)
+{
+    // g^{-1} = (reflections, then the swap): z -> -z maps theta to pi - theta (row N_theta/2 - n),
+    // x -> -x maps phi to pi - phi, y -> -y phi to -phi, x <-> y phi to pi/2 - phi
+    const int np = nphi_n;
+    if (g & 8) n = ntheta / 2 - n;
+    if (g & 2) m = np / 2 - m;
+    if (g & 4) m = -m;
+    if (g & 1) m = np / 4 - m;
+    m %= np;
+    if (m < 0) m += np;
+    return row_off[n] + m;
+}
+
+// Host map offset code (0..342) -> packed table index 16 rep + g (see offset_symmetry), -1 for
+// the inner 27 codes.
 void offset_code_map(int32_t* map)
 {
-    int t = 0;
     for (int c = 0; c < kNumCodes; ++c) {
-        int dx = c % 7 - 3, dy = (c / 7) % 7 - 3, dz = c / 49 - 3;
-        int m = std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz)));
-        map[c] = (m <= 1) ? -1 : t++;
+        int rep, g;
+        map[c] = offset_symmetry(c, &rep, &g) ? kNumSym * rep + g : -1;
     }
 }
 

@@ -138,6 +138,50 @@ def test_every_pair_counted_once():
     assert np.all(cover == 1)
 
 
+# --- symmetric transfer storage (Fig. SemiOctant) ---------------------------------------------
+
+def _sym_index(g, n, m, q):
+    """Direction index of g^{-1}(s) for s = (theta_n, phi_m) on quadrature q; g = swap x <-> y
+    (bit 0) then reflections of x, y, z (bits 1-3), so g^{-1} reflects first and swaps last."""
+    npn = int(q.nphi[n])
+    if g & 8:
+        n = q.ntheta // 2 - n
+    if g & 2:
+        m = npn // 2 - m
+    if g & 4:
+        m = -m
+    if g & 1:
+        m = npn // 4 - m
+    return int(q.row_off[n]) + m % npn
+
+
+def test_transfer_symmetry_34_representatives():
+    """The 316 transfer vectors fall into 34 classes under the quadrature's symmetries (x <-> y,
+    reflections of x, y, z: 16 maps), and T_{g r0}(s) = T_{r0}(g^{-1} s) on the grid, so 34 tables
+    and a direction permutation give all 316. Checked on the oracle's own tables."""
+    from oracle.transfer import transfer_table
+    ka = 6.0
+    q, _ = level_quadrature(ka, 0.8, 1e-8)
+    reps = {}
+    for code in range(343):
+        d = np.array([code % 7 - 3, (code // 7) % 7 - 3, code // 49 - 3])
+        if np.max(np.abs(d)) <= 1:
+            continue
+        ax, ay, az = np.abs(d)
+        key = (max(ax, ay), min(ax, ay), az)
+        g = (1 if ax < ay else 0) | (2 if d[0] < 0 else 0) | (4 if d[1] < 0 else 0) | (8 if d[2] < 0 else 0)
+        reps.setdefault(key, []).append((d, g))
+    assert len(reps) == 34 and sum(len(v) for v in reps.values()) == 316
+    rng = np.random.default_rng(0)
+    keys = sorted(reps)
+    for key in [keys[i] for i in rng.choice(34, 8, replace=False)] + [(3, 3, 3), (2, 0, 0)]:
+        t_rep = transfer_table(ka / 1.0, np.array(key, dtype=float), q)
+        for d, g in reps[key]:
+            t = transfer_table(ka, d.astype(float), q)
+            perm = np.array([_sym_index(g, n, m, q) for n in range(q.nrows) for m in range(int(q.nphi[n]))])
+            assert np.max(np.abs(t - t_rep[perm])) < 1e-12 * np.max(np.abs(t)), (key, tuple(d), g)
+
+
 # --- five-step resample ---------------------------------------------------------------------
 
 @pytest.mark.parametrize("ka_pair", [(2.0, 4.0), (4.0, 2.0), (7.5, 15.0), (15.0, 7.5)])
