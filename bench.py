@@ -147,6 +147,7 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = plan.info()
+    plan_tuning = plan.tuning()
     log("plan fp32 done in %.2fs depth=%d K=%s ell=%s" % (setup_s, info["depth"], info["K"][2:], info["ell"][2:]))
 
     ms = timed(lambda: plan.matvec(q32), args.steps, args.warmup)
@@ -214,8 +215,13 @@ def main():
                              dtype=torch.complex128, device=dev).to(torch.complex64)
         pb = ff.Plan(xt, args.kappa, args.eps, precision="fp32", max_rhs=nb_rhs,
                      depth=args.depth or None)
+        # the library's autotuner picks the launch configuration for 16 right-hand sides (setup)
+        t0 = time.perf_counter()
+        tuned = pb.autotune(qb)
+        tune_s = time.perf_counter() - t0
         msb = timed(lambda: pb.matvec(qb), max(3, args.steps // 2), 1)
-        batched = {"nrhs": nb_rhs, "value": n * nb_rhs / (msb * 1e-3) / 1e6, "ms_per_step": msb}
+        batched = {"nrhs": nb_rhs, "value": n * nb_rhs / (msb * 1e-3) / 1e6, "ms_per_step": msb,
+                   "tuning": tuned, "autotune_s": tune_s}
         if not args.no_cpu:
             ob = pb.matvec(qb)[3].cpu().numpy().astype(np.complex128)
             qh = wl.plane_wave_charges(x, args.kappa, nb_rhs, seed=2)[3]
@@ -335,6 +341,7 @@ def main():
         "rel_err": rel_err,
         "adjoint": {"value": n / (ms_adj * 1e-3) / 1e6, "ms_per_step": ms_adj},
         "setup_s": setup_s,
+        "tuning": plan_tuning,
         "stages_ms": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
         "fp64": fp64,
         "batched": batched,

@@ -167,6 +167,41 @@ enum {
 ffmm_status ffmm_profile_enable(ffmm_plan* plan, int32_t on);
 ffmm_status ffmm_profile_read(ffmm_plan* plan, double* ms, int64_t* calls);
 
+/*
+ * Launch configuration of a plan's kernels. None of it changes what is computed; only the
+ * rounding order of the resample contractions depends on rs_slab. Callers with many right-hand
+ * sides or unusual point sets can let ffmm_plan_autotune choose it.
+ */
+typedef struct {
+    int32_t struct_size;        /* sizeof(ffmm_tuning); set by ffmm_tuning_default */
+    int32_t near_stream;        /* 1 (default): P2P runs on a second stream of the plan, overlapping
+                                   the far-field stages; 0: every stage in order on the caller's stream */
+    int32_t p2p_blocks_per_cu;  /* P2P blocks per compute unit, each looping over leaves (1..16);
+                                   0 (default) = one block per four leaves */
+    int32_t m2l_rhs_block;      /* right-hand sides sharing each transfer-function read in M2L:
+                                   1, 2 or 4; 0 (default) = the largest that does not exceed nrhs */
+    int32_t rs_slab[4];         /* FP32 resample k-slab depth (16, 32 or 64) of step 1, steps 2+3,
+                                   upward steps 4+5 and downward steps 4+5; default 16, 32, 32, 16 */
+} ffmm_tuning;
+
+/* Fill *t with the defaults listed above. t must not be NULL. */
+ffmm_status ffmm_tuning_default(ffmm_tuning* t);
+
+/* Replace the plan's launch configuration (validated; FFMM_ERR_INVALID_ARG for values outside
+ * the ranges above). Takes effect at the next call on the plan. */
+ffmm_status ffmm_plan_set_tuning(ffmm_plan* plan, const ffmm_tuning* t);
+ffmm_status ffmm_plan_get_tuning(const ffmm_plan* plan, ffmm_tuning* out);
+
+/*
+ * Autotuner: time matvecs of the nrhs right-hand sides at d_q (device, layout of ffmm_matvec)
+ * under candidate launch configurations, by coordinate descent over the fields of ffmm_tuning
+ * starting from the plan's current one, and keep the fastest on the plan (also copied to *best
+ * when best is not NULL). d_out receives the products (its contents are those of the last
+ * candidate). Runs about 25 configurations x 4 matvecs, ordered on hip_stream; synchronises it.
+ */
+ffmm_status ffmm_plan_autotune(ffmm_plan* plan, const void* d_q, void* d_out, int32_t nrhs,
+                               void* hip_stream, ffmm_tuning* best);
+
 /* Copy the plan's parameters into *out. */
 ffmm_status ffmm_plan_info_get(const ffmm_plan* plan, ffmm_plan_info* out);
 

@@ -58,6 +58,14 @@ class PlanInfo(ctypes.Structure):
                 ("max_rhs", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("near_stream", ctypes.c_int32),
+                ("p2p_blocks_per_cu", ctypes.c_int32), ("m2l_rhs_block", ctypes.c_int32),
+                ("rs_slab", ctypes.c_int32 * 4)]
+
+
+TUNING_FIELDS = ("near_stream", "p2p_blocks_per_cu", "m2l_rhs_block", "rs_slab")
+
 _P = ctypes.c_void_p
 _SIGS = {
     "ffmm_options_default": [ctypes.POINTER(Options)],
@@ -77,6 +85,10 @@ _SIGS = {
     "ffmm_plan_get_transfer": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "ffmm_plan_get_signature": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "ffmm_profile_enable": [_P, ctypes.c_int32],
+    "ffmm_tuning_default": [ctypes.POINTER(Tuning)],
+    "ffmm_plan_set_tuning": [_P, ctypes.POINTER(Tuning)],
+    "ffmm_plan_get_tuning": [_P, ctypes.POINTER(Tuning)],
+    "ffmm_plan_autotune": [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(Tuning)],
     "ffmm_profile_read": [_P, _P, _P],
 }
 
@@ -285,6 +297,42 @@ class Plan:
         out = np.empty(info["n_boxes"][l] * info["K"][l], np.complex128)
         _check(load_library().ffmm_plan_get_signature(self._h, kind, l, rhs, out.ctypes.data))
         return out.reshape(info["n_boxes"][l], info["K"][l])
+
+    # ---- launch configuration -------------------------------------------------------------
+    @staticmethod
+    def _tuning_dict(t):
+        return {"near_stream": t.near_stream, "p2p_blocks_per_cu": t.p2p_blocks_per_cu,
+                "m2l_rhs_block": t.m2l_rhs_block, "rs_slab": list(t.rs_slab)}
+
+    def tuning(self):
+        """The plan's launch configuration (see ffmm_tuning)."""
+        t = Tuning()
+        _check(load_library().ffmm_plan_get_tuning(self._h, ctypes.byref(t)))
+        return self._tuning_dict(t)
+
+    def set_tuning(self, **fields):
+        """Change fields of the launch configuration (unknown names raise)."""
+        t = Tuning()
+        _check(load_library().ffmm_plan_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in fields.items():
+            if k not in TUNING_FIELDS:
+                raise KeyError(k)
+            if k == "rs_slab":
+                t.rs_slab = (ctypes.c_int32 * 4)(*v)
+            else:
+                setattr(t, k, int(v))
+        _check(load_library().ffmm_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, q):
+        """Time candidate launch configurations on the right-hand sides q (the plan keeps the
+        fastest) and return it."""
+        q2, _ = self._prep(q)
+        out = torch.empty((q2.shape[0], self.n), dtype=self.cdtype, device=q2.device)
+        t = Tuning()
+        _check(load_library().ffmm_plan_autotune(self._h, ctypes.c_void_p(q2.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), q2.shape[0],
+                                                 _stream(), ctypes.byref(t)))
+        return self._tuning_dict(t)
 
     def profile(self, on=True):
         """Record per-stage HIP event times on later calls (see profile_read)."""

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 
@@ -169,6 +170,25 @@ ffmm_status ffmm_options_default(ffmm_options* o)
     return FFMM_OK;
 }
 
+ffmm_status ffmm_tuning_default(ffmm_tuning* t)
+{
+    if (!t) {
+        g_last_error = "tuning pointer is NULL";
+        return FFMM_ERR_INVALID_ARG;
+    }
+    std::memset(t, 0, sizeof(*t));
+    t->struct_size = (int32_t)sizeof(ffmm_tuning);
+    t->near_stream = 1;
+    t->p2p_blocks_per_cu = 0;
+    t->m2l_rhs_block = 0;
+    t->rs_slab[0] = 16;
+    t->rs_slab[1] = 32;
+    t->rs_slab[2] = 32;
+    t->rs_slab[3] = 16;
+    g_last_error.clear();
+    return FFMM_OK;
+}
+
 ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, double eps,
                              const ffmm_options* o, void* hip_stream, ffmm_plan** out)
 {
@@ -213,6 +233,12 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
         p->eps = eps;
         p->opt = opt;
         p->prec = opt.precision;
+        ffmm_tuning_default(&p->tune);
+        {
+            int dev = 0;
+            FFMM_HIP(hipGetDevice(&dev));
+            FFMM_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        }
         build_tree(p, d_points, s);
         build_tables(p, s);
         prepare_rel(p, s);
@@ -272,6 +298,98 @@ ffmm_status ffmm_field_gradient(ffmm_plan* plan, const void* d_q, void* d_grad, 
         run_matvec(plan, d_q, d_grad, nrhs, FFMM_STAGE_ALL, false, true, (hipStream_t)hip_stream);
         plan->has_run = true;
     });
+}
+
+static void check_tuning(const ffmm_tuning* t)
+{
+    if (!t) fail(FFMM_ERR_INVALID_ARG, "tuning is NULL");
+    if (t->struct_size != (int32_t)sizeof(ffmm_tuning))
+        fail(FFMM_ERR_INVALID_ARG, "tuning.struct_size does not match this library");
+    if (t->near_stream != 0 && t->near_stream != 1) fail(FFMM_ERR_INVALID_ARG, "near_stream must be 0 or 1");
+    if (t->p2p_blocks_per_cu < 0 || t->p2p_blocks_per_cu > 16)
+        fail(FFMM_ERR_INVALID_ARG, "p2p_blocks_per_cu must lie in [0, 16]");
+    if (t->m2l_rhs_block != 0 && t->m2l_rhs_block != 1 && t->m2l_rhs_block != 2 && t->m2l_rhs_block != 4)
+        fail(FFMM_ERR_INVALID_ARG, "m2l_rhs_block must be 0, 1, 2 or 4");
+    for (int i = 0; i < 4; ++i)
+        if (t->rs_slab[i] != 16 && t->rs_slab[i] != 32 && t->rs_slab[i] != 64)
+            fail(FFMM_ERR_INVALID_ARG, "rs_slab entries must be 16, 32 or 64");
+}
+
+ffmm_status ffmm_plan_set_tuning(ffmm_plan* p, const ffmm_tuning* t)
+{
+    return guarded([&] {
+        if (!p) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        check_tuning(t);
+        p->tune = *t;
+    });
+}
+
+ffmm_status ffmm_plan_get_tuning(const ffmm_plan* p, ffmm_tuning* out)
+{
+    return guarded([&] {
+        if (!p || !out) fail(FFMM_ERR_INVALID_ARG, "NULL argument");
+        *out = p->tune;
+    });
+}
+
+ffmm_status ffmm_plan_autotune(ffmm_plan* p, const void* d_q, void* d_out, int32_t nrhs,
+                               void* hip_stream, ffmm_tuning* best)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = p ? p->profile : false;
+    ffmm_status st = guarded([&] {
+        check_call(p, d_q, d_out, nrhs);
+        hipStream_t s = (hipStream_t)hip_stream;
+        p->profile = false;
+        FFMM_HIP(hipEventCreate(&e0));
+        FFMM_HIP(hipEventCreate(&e1));
+        // time of one matvec under t: best of three after one warm-up call
+        auto measure = [&](const ffmm_tuning& t) {
+            p->tune = t;
+            run_matvec(p, d_q, d_out, nrhs, FFMM_STAGE_ALL, false, false, s);
+            float best_ms = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                FFMM_HIP(hipEventRecord(e0, s));
+                run_matvec(p, d_q, d_out, nrhs, FFMM_STAGE_ALL, false, false, s);
+                FFMM_HIP(hipEventRecord(e1, s));
+                FFMM_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                FFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                best_ms = std::min(best_ms, ms);
+            }
+            return best_ms;
+        };
+        ffmm_tuning cur = p->tune;
+        if (cur.m2l_rhs_block == 0) cur.m2l_rhs_block = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+        float cur_ms = measure(cur);
+        // coordinate descent: each field in turn over its candidate values
+        auto try_field = [&](int32_t* field, std::initializer_list<int32_t> values) {
+            const int32_t keep = *field;
+            for (int32_t v : values) {
+                if (v == keep) continue;
+                ffmm_tuning t = cur;
+                *(int32_t*)((char*)&t + ((char*)field - (char*)&cur)) = v;
+                const float ms = measure(t);
+                if (ms < cur_ms) {
+                    cur_ms = ms;
+                    cur = t;
+                }
+            }
+        };
+        try_field(&cur.near_stream, {1, 0});
+        try_field(&cur.p2p_blocks_per_cu, {1, 2, 3, 4, 6, 8, 0});
+        if (nrhs >= 2) try_field(&cur.m2l_rhs_block, nrhs >= 4 ? std::initializer_list<int32_t>{1, 2, 4}
+                                                              : std::initializer_list<int32_t>{1, 2});
+        if (p->prec == FFMM_FP32)
+            for (int i = 0; i < 4; ++i) try_field(&cur.rs_slab[i], {16, 32, 64});
+        p->tune = cur;
+        if (best) *best = cur;
+        p->has_run = true;
+    });
+    if (p) p->profile = prof;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return st;
 }
 
 ffmm_status ffmm_plan_info_get(const ffmm_plan* p, ffmm_plan_info* out)

@@ -130,6 +130,8 @@ struct ffmm_plan {
     // so that it overlaps the far-field stages (default priority, non-blocking)
     hipStream_t near_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ffmm_tuning tune{};             // launch configuration (ffmm_plan_set_tuning)
+    int n_cu = 0;                   // compute units of the plan's device
     void* scratch1 = nullptr;       // resample workspaces
     void* scratch2 = nullptr;
     size_t scratch1_bytes = 0, scratch2_bytes = 0;

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
     for (int q = 0; q < RB; ++q) acc[q] = cz<C>();
     // entries in batches of U: all loads of a batch are issued before the first product, so a
     // wave keeps U (T, M) pairs in flight instead of one
-    constexpr int U = RB == 1 ? 8 : 4;
+    constexpr int U = RB == 4 ? 4 : 8;
     int e = 0;
     for (; e + U <= ne; e += U) {
         C t[U], m[U][RB];
@@ -359,14 +359,33 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
     __shared__ C sqa[kWpb][kWave];
     __shared__ C parta[kWpb][NC][kWave];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
-    if (b >= nleaf) return;
     double4* sp = spa[wv];
     C* sq = sqa[wv];
     C (*part)[kWave] = parta[wv];
     const int64_t r = blockIdx.y;
-    const int tb = start[b], tc = count[b];
     const double kappa_rev = kappa / kTwoPi;
+    // A block serves logical blocks of kWpb leaves in a loop (the grid may hold fewer blocks than
+    // there are leaves, so that P2P leaves room for the far-field kernels running beside it). With
+    // a grid of whole XCD rounds each XCD walks a contiguous Morton range.
+    const unsigned nlog = (unsigned)((nleaf + kWpb - 1) / kWpb);
+    constexpr unsigned kXcd = 8;
+    unsigned j0, jstep, jend, base;
+    if (gridDim.x % kXcd == 0) {
+        const unsigned x = blockIdx.x % kXcd, per = nlog / kXcd, rem = nlog % kXcd;
+        base = x * per + min(x, rem);
+        jend = per + (x < rem ? 1 : 0);
+        j0 = blockIdx.x / kXcd;
+        jstep = gridDim.x / kXcd;
+    } else {
+        base = 0;
+        jend = nlog;
+        j0 = blockIdx.x;
+        jstep = gridDim.x;
+    }
+    for (unsigned j = j0; j < jend; j += jstep) {
+    const int64_t b = (int64_t)(base + j) * kWpb + wv;
+    if (b >= nleaf) continue;
+    const int tb = start[b], tc = count[b];
     for (int t0 = 0; t0 < tc; t0 += kWave) {
         // g lanes per target split its sources: chunks of few targets keep the wave busy
         const int tcnt = min(kWave, tc - t0);
@@ -450,6 +469,7 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
             }
         wave_lds_sync();
     }
+    }
 }
 
 // coordinates relative to the leaf centre, in the plan precision
@@ -485,23 +505,28 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         FFMM_LAUNCH_CHECK();
     }
     // P2P needs only the gathered charges: fork it onto the plan's near-field stream
-    if (stages & FFMM_STAGE_NEAR) {
-        hipStream_t sn = p->near_stream;
-        FFMM_HIP(hipEventRecord(p->ev_fork, s));
-        FFMM_HIP(hipStreamWaitEvent(sn, p->ev_fork, 0));
+    const bool fork = (stages & FFMM_STAGE_NEAR) && p->tune.near_stream;
+    auto launch_p2p = [&](hipStream_t sn) {
         StageScope sc(p, FFMM_PROF_P2P, sn);
         const int64_t nl = p->lev[L].n;
+        const int64_t nlog = (nl + kWpb - 1) / kWpb;
+        const int bpc = p->tune.p2p_blocks_per_cu;
+        const unsigned grid = (unsigned)(bpc > 0 ? std::min<int64_t>(nlog, (int64_t)p->n_cu * bpc) : nlog);
         if (gradient)
-            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, sn,
+            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn,
                                p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
                                phin, n, (int64_t)nl);
         else
-            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(nblk(nl, kWpb), nrhs), dim3(kWave * kWpb), 0, sn,
+            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn,
                                p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
                                phin, n, (int64_t)nl);
         FFMM_LAUNCH_CHECK();
+    };
+    if (fork) {
+        FFMM_HIP(hipEventRecord(p->ev_fork, s));
+        FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
+        launch_p2p(p->near_stream);
     }
-
     if (stages & FFMM_STAGE_FAR) {
         LevelData& leaf = p->lev[L];
         // P2M
@@ -519,18 +544,25 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
             run_resample(p, l, l - 1, nrhs, s);
         }
         // M2L, l = 2..L (written into the L buffers, which then receive the downward pass)
+        int rb = p->tune.m2l_rhs_block;
+        if (rb == 0) rb = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
         for (int l = 2; l <= L; ++l) {
             StageScope sc(p, l == L ? FFMM_PROF_LEAF_M2L : FFMM_PROF_M2L, s);
             LevelData& Lv = p->lev[l];
             const int kch = (Lv.K + 255) / 256;
             const unsigned gx = (unsigned)(Lv.n * kch);
-            if (nrhs >= 4)
-                hipLaunchKernelGGL((m2l_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), dim3(256), 0, s,
-                                   Lv.K, kch, Lv.il_ptr, Lv.il_src, Lv.il_tix, Lv.tperm,
-                                   (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+            const dim3 grid(gx, (nrhs + rb - 1) / rb);
+            if (rb == 4)
+                hipLaunchKernelGGL((m2l_kernel<C, 4>), grid, dim3(256), 0, s, Lv.K, kch, Lv.il_ptr,
+                                   Lv.il_src, Lv.il_tix, Lv.tperm, (const C*)Lv.transfer,
+                                   (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+            else if (rb == 2)
+                hipLaunchKernelGGL((m2l_kernel<C, 2>), grid, dim3(256), 0, s, Lv.K, kch, Lv.il_ptr,
+                                   Lv.il_src, Lv.il_tix, Lv.tperm, (const C*)Lv.transfer,
+                                   (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
             else
-                hipLaunchKernelGGL((m2l_kernel<C, 1>), dim3(gx, nrhs), dim3(256), 0, s, Lv.K, kch,
-                                   Lv.il_ptr, Lv.il_src, Lv.il_tix, Lv.tperm, (const C*)Lv.transfer,
+                hipLaunchKernelGGL((m2l_kernel<C, 1>), grid, dim3(256), 0, s, Lv.K, kch, Lv.il_ptr,
+                                   Lv.il_src, Lv.il_tix, Lv.tperm, (const C*)Lv.transfer,
                                    (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
             FFMM_LAUNCH_CHECK();
         }
@@ -553,10 +585,12 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                phis, n, leaf.n);
         FFMM_LAUNCH_CHECK();
     }
-    if (stages & FFMM_STAGE_NEAR) {
+    if (fork) {
         // join: the scatter waits for P2P (and the next call's gather for this P2P's reads of qs)
         FFMM_HIP(hipEventRecord(p->ev_join, p->near_stream));
         FFMM_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
+    } else if (stages & FFMM_STAGE_NEAR) {
+        launch_p2p(s);
     }
     {
         StageScope sc(p, FFMM_PROF_SCATTER, s);

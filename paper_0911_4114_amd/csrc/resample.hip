@@ -797,10 +797,6 @@ template <class F> void with_ks(int ks, F&& f)
         f(KsTag<64>{});
 }
 
-// slab depth per kernel (measured on the 2^20-point sphere at kappa 177: the row steps favour
-// shallow slabs, the circle step and the upward step 5 deeper ones)
-constexpr int kKsRs1 = 16, kKsRs3 = 32, kKsRs5Up = 32, kKsRs5Down = 16;
-
 void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
 {
     const bool up = l_dst == l_src - 1;
@@ -816,7 +812,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ntj = cdiv(NA, MN);
         dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_src, nrhs);
         if (up)
-            with_ks(kKsRs1, [&](auto t) {
+            with_ks(p->tune.rs_slab[0], [&](auto t) {
                 hipLaunchKernelGGL((rs1_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
                                    (const float*)rs.d1, (const float2*)S.sigM, S.K, S.n,
@@ -824,7 +820,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
                                    (const float2*)nullptr, G1);
             });
         else
-            with_ks(kKsRs1, [&](auto t) {
+            with_ks(p->tune.rs_slab[0], [&](auto t) {
                 hipLaunchKernelGGL((rs1_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
                                    (const float*)rs.d1, (const float2*)S.sigL, S.K, S.n, Cl.parent,
@@ -834,7 +830,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     }
     {
         dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(rs.nt_dst, MM), nrhs);
-        with_ks(kKsRs3, [&](auto t) {
+        with_ks(p->tune.rs_slab[1], [&](auto t) {
             hipLaunchKernelGGL((rs3_mfma<decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
                                rs.nt_src, rs.nt_dst, rs.nt_dth, (const float*)rs.dth, (const float2*)G1,
                                G2);
@@ -847,7 +843,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ntj = cdiv(mx, MN);
         if (up) {
             dim3 grid((unsigned)rs.ntiles, ntj * rs.rows_dst, nrhs);
-            with_ks(kKsRs5Up, [&](auto t) {
+            with_ks(p->tune.rs_slab[2], [&](auto t) {
                 hipLaunchKernelGGL((rs5_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
                                    rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5,
                                    (const float2*)G2, D.K, rs.tile_begin, rs.tile_end, Cl.parent,
@@ -856,7 +852,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
             });
         } else {
             dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_dst, nrhs);
-            with_ks(kKsRs5Down, [&](auto t) {
+            with_ks(p->tune.rs_slab[3], [&](auto t) {
                 hipLaunchKernelGGL((rs5_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
                                    rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5,
                                    (const float2*)G2, D.K, (const int32_t*)nullptr,

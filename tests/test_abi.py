@@ -40,6 +40,19 @@ def test_options_default_and_status_strings():
         assert lib.ffmm_status_string(code)
 
 
+def test_tuning_default_and_null_plan():
+    lib = ff.load_library()
+    t = ff.Tuning()
+    assert lib.ffmm_tuning_default(ctypes.byref(t)) == 0
+    assert t.struct_size == ctypes.sizeof(ff.Tuning)
+    assert (t.near_stream, t.p2p_blocks_per_cu, t.m2l_rhs_block) == (1, 0, 0)
+    assert list(t.rs_slab) == [16, 32, 32, 16]
+    assert lib.ffmm_tuning_default(None) == -1
+    assert lib.ffmm_plan_set_tuning(None, ctypes.byref(t)) == -1
+    assert lib.ffmm_plan_get_tuning(None, ctypes.byref(t)) == -1
+    assert lib.ffmm_plan_autotune(None, None, None, 1, None, None) == -1
+
+
 @pytest.mark.parametrize("ka", [1.95, 2.77, 3.14, 5.54, 11.1, 22.1, 44.3])
 @pytest.mark.parametrize("eps,prec", [(1e-3, 1), (1e-4, 1), (1e-6, 0), (1e-8, 0)])
 def test_host_parameter_choice_matches_oracle(ka, eps, prec):

@@ -92,3 +92,38 @@ def test_autograd_matches_oracle_gradients(setup):
     ex = rel_l2(xq.grad.cpu().numpy(), gx)
     log("autograd errs q %.3e x %.3e" % (eq, ex))
     assert eq < 1e-5 and ex < 1e-4
+
+
+def test_launch_configurations_agree_and_autotune(setup):
+    """Launch configurations change no result beyond the resample's rounding order; the
+    autotuner keeps a valid configuration that gives the same products."""
+    x, xt = setup
+    n = len(x)
+    Q = wl.complex_normal(n, seed=11, nrhs=4)
+    p = ff.Plan(xt, KAPPA, 1e-4, precision="fp32", max_rhs=4)
+    q = dev_complex(Q, True)
+    base = p.matvec(q).cpu().numpy()
+    # the P2P placement and stream overlap leave every operation and its order unchanged
+    for cfg in ({"near_stream": 0}, {"p2p_blocks_per_cu": 0}, {"p2p_blocks_per_cu": 1},
+                {"near_stream": 1, "p2p_blocks_per_cu": 5}):
+        p.set_tuning(**cfg)
+        assert np.array_equal(p.matvec(q).cpu().numpy(), base), cfg
+    # other slab depths and RHS blocking: same operator, FP32 rounding
+    for cfg in ({"m2l_rhs_block": 1}, {"m2l_rhs_block": 2}, {"rs_slab": [64, 64, 64, 64]},
+                {"rs_slab": [16, 16, 16, 16]}):
+        p.set_tuning(**cfg)
+        got = p.matvec(q).cpu().numpy()
+        assert rel_l2(got, base) < 1e-6, (cfg, rel_l2(got, base))
+    with pytest.raises(ff.FfmmError):
+        p.set_tuning(rs_slab=[8, 16, 16, 16])
+    with pytest.raises(ff.FfmmError):
+        p.set_tuning(m2l_rhs_block=3)
+    best = p.autotune(q)
+    log("autotuned: %s" % best)
+    assert best == p.tuning()
+    assert best["m2l_rhs_block"] in (1, 2, 4) and best["near_stream"] in (0, 1)
+    got = p.matvec(q).cpu().numpy()
+    assert rel_l2(got, base) < 1e-6
+    tg = wl.subset(n, 300)
+    ref = direct.matvec(x, Q[2], KAPPA, targets=tg)
+    assert rel_l2(got[2][tg], ref) < 1e-4
