@@ -86,6 +86,11 @@ struct Resampler {
     void* d1 = nullptr;             // step 1, per source row n: [N_phi,n][nphi_all] (j fastest)
     void* dth = nullptr;            // step 3: [nt_src][nt_dth] (t' fastest, zero-padded)
     int nt_dth = 0;                 // row stride of dth: nt_dst rounded up to a multiple of 4
+    // the theta step on half ranges (eqn. FourierSphereSym), FP32 path: operators for the even
+    // and the odd parts of the phi columns, rows 0..N_theta/2 -> 0..N'_theta/2, each
+    // [nt_src/2+1][ldh] (zero-padded), the even one first, the factor 1/2 of the split folded in
+    void* dth_h = nullptr;
+    int ldh = 0;
     void* d5 = nullptr;             // step 5, per dest row n': [nphi_all][N'_phi,n'] (j' fastest)
     int32_t* d_src_row_off = nullptr;
     int32_t* d_src_nphi = nullptr;

@@ -357,6 +357,25 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     }
     upload_real<R>(p->arena, &rs.d1, d1, s);
     upload_real<R>(p->arena, &rs.dth, dth, s);
+    {
+        // half-range theta operators: an even (odd) circle sequence x, x(N - t) = +-x(t), is
+        // resampled by sum over the half range of x(t) (D[t][t'] +- D[N - t][t']), the rows t = 0,
+        // N/2 counted once (even) or vanishing (odd)
+        const int ns = rs.nt_src, nsh = ns / 2 + 1, ndh = rs.nt_dst / 2 + 1;
+        rs.ldh = (ndh + 3) / 4 * 4;
+        std::vector<double> dh(2 * (size_t)nsh * rs.ldh, 0.0);
+        double* de = dh.data();
+        double* dodd = dh.data() + (size_t)nsh * rs.ldh;
+        for (int t = 0; t < nsh; ++t)
+            for (int tp = 0; tp < ndh; ++tp) {
+                const double a = dth[(size_t)t * rs.nt_dth + tp];
+                const bool edge = (t == 0 || 2 * t == ns);
+                const double b = edge ? 0.0 : dth[(size_t)(ns - t) * rs.nt_dth + tp];
+                de[(size_t)t * rs.ldh + tp] = 0.5 * (a + b);
+                dodd[(size_t)t * rs.ldh + tp] = edge ? 0.0 : 0.5 * (a - b);
+            }
+        upload_real<R>(p->arena, &rs.dth_h, dh, s);
+    }
     upload_real<R>(p->arena, &rs.d5, d5, s);
     rs.d_src_row_off = S.d_row_off;
     rs.d_src_nphi = S.d_nphi;

@@ -461,55 +461,25 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int
     }
 }
 
-// steps 2 + 3 staging: A = theta resample matrix (t' fastest), B = circle data of 32 columns
-template <int KS> struct Rs3Stage {
-    static constexpr int QA = KS / 16, QB = KS / 8;
-    int tid, ntS, ldth, i0, half, NA;
-    const float* dth;
-    const float2* sbase;   // this thread's staged column (phi_m of its box), row 0
-    bool scol_ok;
-    float4 ra[QA];
-    float2 rb[QB];
-    bool oka[QA], okb[QB];
-    __device__ void load(int k0)
-    {
-#pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            const int e = tid + NT * q, t = k0 + (e >> 4), tp = i0 + 4 * (e & 15);
-            const bool ok = t < ntS && tp < ldth;
-            ra[q] = *(const float4*)(dth + (ok ? (int64_t)t * ldth + tp : 0));
-            oka[q] = ok;
-        }
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            const int tt = k0 + (tid >> 5) + 8 * q;
-            const int t = min(tt, ntS - 1);
-            const bool lo = t <= ntS / 2;
-            rb[q] = sbase[(int64_t)(lo ? t : ntS - t) * NA + (lo ? 0 : half)];
-            okb[q] = tt < ntS && scol_ok;
-        }
-    }
-    __device__ void store(float* As, float* Bs)
-    {
-#pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            const int e = tid + NT * q;
-            *(float4*)&As[(e >> 4) * MAP + 4 * (e & 15)] = oka[q] ? ra[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            *(float2*)&Bs[((tid >> 5) + 8 * q) * MBP + 2 * (tid & 31)] = okb[q] ? rb[q] : make_float2(0.f, 0.f);
-        }
-    }
-};
-
+// steps 2 + 3 on half ranges (eqn. FourierSphereSym): per phi column m < NPhi/2 the source rows
+// 0..N_theta/2 split into u = F_m + F_{m + NPhi/2} (even phi modes, even in theta) and
+// v = F_m - F_{m + NPhi/2} (odd modes, odd in theta); the theta step is then two half-range
+// contractions u' = De^T u, v' = Do^T v (De, Do carry the factor 1/2) onto the destination rows
+// 0..N'_theta/2, where F'_m = u' + v', F'_{m + NPhi/2} = u' - v' (formed by steps 4 + 5). Half the
+// work of resampling the full theta circle. A block tile stacks 32 rows t' of De (the waves on
+// tile rows 0..31, which read u) over the same 32 rows of Do (tile rows 32..63, which read v).
+// G2 of the FP32 path: [rhs][box][N'_theta/2 + 1][2][NPhi/2] complex: u' then v' of each row.
+// dh holds De then Do, each [N_theta/2 + 1][ldh].
 template <int KS>
-__global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, int ntS, int ntD, int ldth,
-                                               const float* __restrict__ dth,
-                                               const float2* __restrict__ G1, float2* __restrict__ G2)
+__global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, int ntSh, int ntDh,
+                                                int ldh, const float* __restrict__ dh,
+                                                const float2* __restrict__ G1, float2* __restrict__ G2)
 {
+    constexpr int QA = KS / 16, QB = KS / 8;
+    __shared__ __align__(16) float As[KS * MAP];
+    __shared__ __align__(16) float Bs[2 * KS * MBP];
     const int half = NA / 2;
-    const int i0 = blockIdx.y * MM;
+    const int i0 = blockIdx.y * (MM / 2);
     const int64_t r = blockIdx.z;
     const int64_t ncols = nb * half;
     const int64_t g0 = (int64_t)blockIdx.x * (MN / 2);
@@ -517,18 +487,12 @@ __global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, in
     const int m0 = (int)(g0 - cbase * half);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    __shared__ __align__(16) float As[KS * MAP];
-    __shared__ __align__(16) float Bs[KS * MBP];
-    Rs3Stage<KS> st;
-    st.tid = tid;
-    st.ntS = ntS;
-    st.ldth = ldth;
-    st.i0 = i0;
-    st.half = half;
-    st.NA = NA;
-    st.dth = dth;
+    const bool odd = wr != 0;
+    const int64_t mat_off = (int64_t)ntSh * ldh;   // Do after De
+    // this thread's staged column (phi_m of its box), row 0
+    const float2* sbase;
+    bool scol_ok;
     {
-        // the staged column of this thread: (box, phi index) of column g0 + tid % 32
         const int cc = tid & 31;
         int m = m0 + cc;
         int64_t c = cbase;
@@ -536,11 +500,68 @@ __global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, in
             m -= half;
             ++c;
         }
-        st.scol_ok = g0 + cc < ncols;
-        st.sbase = st.scol_ok ? G1 + (r * nb + c) * rowsS * NA + m : G1;
+        scol_ok = g0 + cc < ncols;
+        sbase = scol_ok ? G1 + (r * nb + c) * rowsS * NA + m : G1;
     }
+    float4 ra[QA];
+    float4 rab[QB];   // (F_m, F_{m + NPhi/2}) of each staged row
+    bool oka[QA], okb[QB];
+    auto load = [&](int k0) {
+        // A tile column c4: 0..31 are De rows i0.., 32..63 the same rows of Do
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q, t = k0 + (e >> 4), c4 = 4 * (e & 15);
+            const int tp = i0 + (c4 & 31);
+            const bool ok = t < ntSh && tp < ldh;
+            const int64_t idx = ok ? (c4 >= 32 ? mat_off : 0) + (int64_t)t * ldh + tp : 0;
+            ra[q] = *(const float4*)(dh + idx);
+            oka[q] = ok;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int tt = k0 + (tid >> 5) + 8 * q;
+            const int64_t row = (int64_t)min(tt, ntSh - 1) * NA;
+            const float2 a = sbase[row], b = sbase[row + half];
+            rab[q] = make_float4(a.x, a.y, b.x, b.y);
+            okb[q] = tt < ntSh && scol_ok;
+        }
+    };
+    // invalid entries become zeros component by component (a select of whole vectors makes the
+    // compiler stage them through private memory)
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + NT * q;
+            const float4 v = ra[q];
+            const bool ok = oka[q];
+            *(float4*)&As[(e >> 4) * MAP + 4 * (e & 15)] =
+                make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int o = ((tid >> 5) + 8 * q) * MBP + 2 * (tid & 31);
+            const float4 ab = rab[q];
+            const bool ok = okb[q];
+            *(float2*)&Bs[o] = make_float2(ok ? ab.x + ab.z : 0.f, ok ? ab.y + ab.w : 0.f);
+            *(float2*)&Bs[KS * MBP + o] = make_float2(ok ? ab.x - ab.z : 0.f, ok ? ab.y - ab.w : 0.f);
+        }
+    };
     f32x16 acc = {};
-    mfma_mainloop<KS>(st, As, Bs, ntS, acc, wr, wc, lane);
+    const int nslab = (ntSh + KS - 1) / KS;
+    load(0);
+    store();
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        const bool more = sl + 1 < nslab;
+        if (more) load((sl + 1) * KS);
+        const int kc = (min(KS, ntSh - sl * KS) + 7) & ~7;
+        mfma_slab(As, Bs + (odd ? KS * MBP : 0), acc, wr, wc, lane, kc);
+        if (more) {
+            __syncthreads();
+            store();
+        }
+        __syncthreads();
+    }
     const int col = wc + (lane & 31), cc = col >> 1, part = col & 1;
     if (g0 + cc >= ncols) return;
     int m = m0 + cc;
@@ -549,20 +570,20 @@ __global__ __launch_bounds__(NT) void rs3_mfma(int64_t nb, int NA, int rowsS, in
         m -= half;
         ++c;
     }
-    float* base = (float*)(G2 + (r * nb + c) * ntD * half + m) + part;
+    float* base = (float*)(G2 + ((r * nb + c) * ntDh * 2 + (odd ? 1 : 0)) * half + m) + part;
     const int h = lane >> 5;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int tp = i0 + wr + (q >> 2) * 8 + h * 4 + (q & 3);
-        if (tp < ntD) base[(int64_t)tp * half * 2] = acc[q];
+        const int tp = i0 + (q >> 2) * 8 + h * 4 + (q & 3);
+        if (tp < ntDh) base[(int64_t)tp * 2 * half * 2] = acc[q];
     }
 }
 
-// steps 4 + 5 staging: A = the destination row's samples on the common phi grid (rows n' and
-// N'_theta - n' of the theta-resampled data), B = the Dirichlet block of the destination row
+// steps 4 + 5 staging: A = the destination row's samples on the common phi grid (row n' of the
+// half-range theta output), B = the Dirichlet block of the destination row
 template <int KS> struct Rs5Stage {
     static constexpr int QA = KS / 8, QB = KS / 16;
-    int tid, NA, half, row, tneg, ntD, len, j0;
+    int tid, NA, row, ntDh, len, j0;
     int64_t cb, ce, nb, r;
     const float2* G2;
     const float* D;
@@ -576,8 +597,11 @@ template <int KS> struct Rs5Stage {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
             const int j = min(k0 + kk, NA - 1);
             const int64_t c = min(cb + bc, ce - 1);
-            const float2* g = G2 + (r * nb + c) * ntD * half;
-            ra[q] = (j < half) ? g[(int64_t)row * half + j] : g[(int64_t)tneg * half + (j - half)];
+            // row n' on the common phi grid: u' + v' (j < NPhi/2), u' - v' (j >= NPhi/2)
+            const int half = NA / 2, jj = j < half ? j : j - half;
+            const float2* g = G2 + ((r * nb + c) * ntDh + row) * 2 * half + jj;
+            const float2 u = g[0], v = g[half];
+            ra[q] = j < half ? make_float2(u.x + v.x, u.y + v.y) : make_float2(u.x - v.x, u.y - v.y);
             oka[q] = k0 + kk < NA && cb + bc < ce;
         }
 #pragma unroll
@@ -632,10 +656,8 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     Rs5Stage<KS> st;
     st.tid = tid;
     st.NA = NA;
-    st.half = NA / 2;
     st.row = row;
-    st.tneg = (ntD - row) % ntD;
-    st.ntD = ntD;
+    st.ntDh = ntD / 2 + 1;
     st.len = len;
     st.j0 = j0;
     st.cb = cb;
@@ -829,11 +851,11 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         FFMM_LAUNCH_CHECK();
     }
     {
-        dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(rs.nt_dst, MM), nrhs);
+        const int ntSh = rs.nt_src / 2 + 1, ntDh = rs.nt_dst / 2 + 1;
+        dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(ntDh, MM / 2), nrhs);
         with_ks(p->tune.rs_slab[1], [&](auto t) {
-            hipLaunchKernelGGL((rs3_mfma<decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
-                               rs.nt_src, rs.nt_dst, rs.nt_dth, (const float*)rs.dth, (const float2*)G1,
-                               G2);
+            hipLaunchKernelGGL((rs3h_mfma<decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
+                               ntSh, ntDh, rs.ldh, (const float*)rs.dth_h, (const float2*)G1, G2);
         });
         FFMM_LAUNCH_CHECK();
     }

@@ -5,7 +5,7 @@ import pytest
 from oracle import direct, tree as otree
 from oracle.ffmm import Plan
 from oracle.quadrature import level_quadrature
-from oracle.resample import resample_sig
+from oracle.resample import resample_sig, resample_sig_fourier_sym
 
 
 def _cube(n, seed=0):
@@ -221,6 +221,24 @@ def test_five_step_resample_plane_wave():
     f2 = np.exp(1j * 6.0 * q2.dirs() @ d)
     assert np.allclose(resample_sig(f1, q1, q2), f2, atol=1e-10)
     assert np.allclose(resample_sig(f2, q2, q1), f1, atol=1e-10)
+
+
+@pytest.mark.parametrize("ka_pair", [(2.0, 4.0), (4.0, 2.0), (7.5, 15.0), (15.0, 7.5)])
+def test_fourier_sym_variant_equals_five_steps(ka_pair):
+    """The variant built on eqn. FourierSphereSym (even/odd theta parts of the phi columns, each
+    resampled on the half range) gives the five-step result on data with the sphere symmetry,
+    with the smaller common phi length too."""
+    q1, _ = level_quadrature(ka_pair[0], 0.8, 1e-6)
+    q2, _ = level_quadrature(ka_pair[1], 0.8, 1e-6)
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((2, q1.K)) + 1j * rng.standard_normal((2, q1.K))
+    for n in (0, q1.nrows - 1):
+        a, b = q1.row_off[n], q1.row_off[n + 1]
+        f[:, a:b] = 0.5 * (f[:, a:b] + np.roll(f[:, a:b], (b - a) // 2, axis=-1))
+    ref = resample_sig(f, q1, q2)
+    for na in (None, min(int(q1.nphi.max()), int(q2.nphi.max()))):
+        got = resample_sig_fourier_sym(f, q1, q2, nphi_all=na)
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref)), na
 
 
 def test_five_step_resample_uniform_rows_roundtrip():
