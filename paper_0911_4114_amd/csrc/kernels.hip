@@ -504,7 +504,7 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                            p->perm, n, conj_io ? 1 : 0, qs);
         FFMM_LAUNCH_CHECK();
     }
-    // P2P needs only the gathered charges: fork it onto the plan's near-field stream
+    // P2P needs only the gathered charges: it runs on the plan's near-field stream
     const bool fork = (stages & FFMM_STAGE_NEAR) && p->tune.near_stream;
     auto launch_p2p = [&](hipStream_t sn) {
         StageScope sc(p, FFMM_PROF_P2P, sn);
@@ -522,7 +522,7 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                phin, n, (int64_t)nl);
         FFMM_LAUNCH_CHECK();
     };
-    if (fork) {
+    if (fork && !(stages & FFMM_STAGE_FAR)) {
         FFMM_HIP(hipEventRecord(p->ev_fork, s));
         FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
         launch_p2p(p->near_stream);
@@ -537,6 +537,12 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                leaf.K, kch, (const R*)leaf.dirs, kfac, p->leaf_start, p->leaf_count,
                                (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n);
             FFMM_LAUNCH_CHECK();
+        }
+        // P2P forks after P2M, so that the first far-field kernel is not queued behind it
+        if (fork) {
+            FFMM_HIP(hipEventRecord(p->ev_fork, s));
+            FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
+            launch_p2p(p->near_stream);
         }
         // M2M, l = L..3 (five-step resample to the parent grid, translate, sum children)
         for (int l = L; l >= 3; --l) {
