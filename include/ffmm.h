@@ -179,9 +179,14 @@ typedef struct {
     int32_t p2p_blocks_per_cu;  /* P2P blocks per compute unit, each looping over leaves (1..16);
                                    0 (default) = one block per four leaves */
     int32_t m2l_rhs_block;      /* right-hand sides sharing each transfer-function read in M2L:
-                                   1, 2 or 4; 0 (default) = the largest that does not exceed nrhs */
+                                   1, 2 or 4 (at most 2 with m2l_by_parent); 0 (default) = the
+                                   largest that does not exceed nrhs */
     int32_t rs_slab[4];         /* FP32 resample k-slab depth (16, 32 or 64) of step 1, steps 2+3,
                                    upward steps 4+5 and downward steps 4+5; default 16, 32, 32, 16 */
+    int32_t m2l_by_parent;      /* 1: M2L by parent pairs, each source signature and transfer
+                                   function read once per parent pair (pays where parents hold
+                                   many children: volume distributions); 0 (default): one target
+                                   box per block over its interaction list */
 } ffmm_tuning;
 
 /* Fill *t with the defaults listed above. t must not be NULL. */

@@ -61,6 +61,7 @@ struct LevelData {
     int32_t* il_src = nullptr;      // [n_il]
     int32_t* il_code = nullptr;     // [n_il] offset code 0..342
     int32_t* il_tix = nullptr;      // [n_il] 16 rep + g: representative table and symmetry (tsym)
+    int32_t* nb_slots = nullptr;    // levels 1..L-1: [n][27] box at offset (dx,dy,dz), -1 if none
     // quadrature (levels >= 2)
     LevelParams par;
     int K = 0;
@@ -136,6 +137,7 @@ struct ffmm_plan {
     hipStream_t near_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ffmm_tuning tune{};             // launch configuration (ffmm_plan_set_tuning)
+    int32_t* code_map = nullptr;    // [343] offset code -> 16 rep + g, -1 for the inner codes
     int n_cu = 0;                   // compute units of the plan's device
     void* scratch1 = nullptr;       // resample workspaces
     void* scratch2 = nullptr;

@@ -252,6 +252,126 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
 }
 
 // ------------------------------------------------------------------------------------------
+// M2L by parent pairs: the same I_b(s_k) = sum_{e in I(b)} M_src(e)(s_k) T_off(e)(s_k), organised
+// by the definition of I(b) (Section 2): the children b of a parent P receive from the children
+// b' of every neighbour P' of P that are not neighbours of b. For P' at offset D from P and
+// octants o(b), o(b'), the transfer vector is 2D + (o(b') - o(b)), one of 27 per D; so a block
+// (P, 256 directions) loads the <= 8 source signatures of each P' once and each of the 27
+// transfer functions once, and applies them to every child pair they serve (up to 64 pairs),
+// instead of reading one M and one T per pair. T is read through the quadrature symmetry as in
+// m2l_kernel.
+// ------------------------------------------------------------------------------------------
+template <class C, int RB>
+__global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
+                                                   const int32_t* __restrict__ pslots,
+                                                   const int32_t* __restrict__ child_start,
+                                                   const int32_t* __restrict__ child_count,
+                                                   const int32_t* __restrict__ octant,
+                                                   const int32_t* __restrict__ code_map,
+                                                   const int32_t* __restrict__ tperm,
+                                                   const C* __restrict__ T, const C* __restrict__ M,
+                                                   C* __restrict__ out, int64_t nb, int nrhs)
+{
+    // per occupied neighbour P' of P (compacted): D, first child, octant mask of its children;
+    // the transfer-table index of each of its 27 child-offset differences
+    __shared__ int32_t s_d[27], s_sb[27], s_sm[27], s_tx[27][27];
+    __shared__ int32_t s_n, s_tmask;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t P = lb / kchunks;
+    const int kraw = (lb % kchunks) * 256 + threadIdx.x;
+    const bool kvalid = kraw < K;
+    const int k = kvalid ? kraw : K - 1;   // tail lanes compute on a valid direction, store nothing
+    const int r0 = blockIdx.y * RB;
+    const int tb = child_start[P], tn = child_count[P];
+    if (threadIdx.x == 0) {
+        int n = 0, tm = 0;
+        for (int i = 0; i < tn; ++i) tm |= 1 << octant[tb + i];
+        for (int D = 0; D < 27; ++D) {
+            const int Pn = pslots[P * 27 + D];
+            if (Pn < 0) continue;
+            const int sb = child_start[Pn], sn = child_count[Pn];
+            int sm = 0;
+            for (int i = 0; i < sn; ++i) sm |= 1 << octant[sb + i];
+            s_d[n] = D;
+            s_sb[n] = sb;
+            s_sm[n] = sm;
+            ++n;
+        }
+        s_n = n;
+        s_tmask = tm;
+    }
+    __syncthreads();
+    const int nn = s_n;
+    for (int t = threadIdx.x; t < nn * 27; t += 256) {
+        const int i = t / 27, e = t % 27, D = s_d[i];
+        const int code = (2 * (D % 3 - 1) + e % 3 - 1 + 3) + 7 * (2 * ((D / 3) % 3 - 1) + (e / 3) % 3 - 1 + 3) +
+                         49 * (2 * (D / 9 - 1) + e / 9 - 1 + 3);
+        s_tx[i][e] = code_map[code];
+    }
+    __syncthreads();
+    const int64_t plane = nb * (int64_t)K;
+    const int nr = min(RB, nrhs - r0);
+    int kp[kNumSym];
+#pragma unroll
+    for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[g * K + k];
+    const int tmask = s_tmask;
+    C acc[8][RB];
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[o][q] = cz<C>();
+    for (int i = 0; i < nn; ++i) {
+        const int sb = s_sb[i], smask = s_sm[i];
+        // source signatures of the occupied octants
+        C ms[8][RB];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            if (!((smask >> o) & 1)) continue;
+            const int ci = sb + __builtin_popcount(smask & ((1 << o) - 1));
+            const C* mp = M + (int64_t)r0 * plane + (uint64_t)(uint32_t)ci * (uint32_t)K + k;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) ms[o][q] = (q < nr) ? mp[(int64_t)q * plane] : cz<C>();
+        }
+#pragma unroll
+        for (int e = 0; e < 27; ++e) {
+            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+            // octant pairs (ot, ot + e) present on both sides
+            int pairs = 0;
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot) {
+                const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
+                if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
+                pairs |= ((tmask >> ot) & (smask >> (ax + 2 * ay + 4 * az)) & 1) << ot;
+            }
+            if (!pairs) continue;
+            const int tx = __builtin_amdgcn_readfirstlane(s_tx[i][e]);
+            if (tx < 0) continue;   // a neighbour of the target: near field
+            const C tv = T[(uint64_t)(uint32_t)(tx >> 4) * (uint32_t)K + kp[tx & (kNumSym - 1)]];
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot) {
+                const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
+                if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
+                if (!((pairs >> ot) & 1)) continue;
+                const int os = ax + 2 * ay + 4 * az;
+#pragma unroll
+                for (int q = 0; q < RB; ++q) cmac(acc[ot][q], ms[os][q], tv);
+            }
+        }
+    }
+    if (!kvalid) return;
+    for (int i = 0; i < tn; ++i) {
+        const int c = tb + i;
+        const int o = __builtin_amdgcn_readfirstlane(octant[c]);
+#pragma unroll
+        for (int oo = 0; oo < 8; ++oo)
+            if (oo == o)
+#pragma unroll
+                for (int q = 0; q < RB; ++q)
+                    if (q < nr) out[(int64_t)(r0 + q) * plane + (int64_t)c * K + k] = acc[oo][q];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // L2P (far part of eqn. FMM_FinalStep): phi_i += sum_k w_k L_b(s_k) e^{i kappa s_k.(c_b - x_i)};
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
 // One wave per leaf box (four per block), one lane per target point; w_k L_b(s_k) and s_k are
@@ -555,7 +675,22 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         for (int l = 2; l <= L; ++l) {
             StageScope sc(p, l == L ? FFMM_PROF_LEAF_M2L : FFMM_PROF_M2L, s);
             LevelData& Lv = p->lev[l];
+            LevelData& Pv = p->lev[l - 1];
             const int kch = (Lv.K + 255) / 256;
+            if (p->tune.m2l_by_parent) {
+                const int rbp = rb >= 2 ? 2 : 1;
+                const dim3 grid((unsigned)(Pv.n * kch), (nrhs + rbp - 1) / rbp);
+                if (rbp == 2)
+                    hipLaunchKernelGGL((m2lp_kernel<C, 2>), grid, dim3(256), 0, s, Lv.K, kch, Pv.nb_slots,
+                                       Pv.child_start, Pv.child_count, Lv.octant, p->code_map, Lv.tperm,
+                                       (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                else
+                    hipLaunchKernelGGL((m2lp_kernel<C, 1>), grid, dim3(256), 0, s, Lv.K, kch, Pv.nb_slots,
+                                       Pv.child_start, Pv.child_count, Lv.octant, p->code_map, Lv.tperm,
+                                       (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                FFMM_LAUNCH_CHECK();
+                continue;
+            }
             const unsigned gx = (unsigned)(Lv.n * kch);
             const dim3 grid(gx, (nrhs + rb - 1) / rb);
             if (rb == 4)

@@ -384,6 +384,28 @@ __global__ void neighbour_lists(const uint64_t* __restrict__ keys, int64_t n, in
         for (int i = 0; i < c; ++i) src[ptr[b] + i] = nb[i];
 }
 
+// The 27 neighbour slots of every box of level l: slot (dx+1) + 3(dy+1) + 9(dz+1) holds the index
+// of the box at offset (dx, dy, dz), -1 where that box is empty or outside the root.
+__global__ void neighbour_slots(const uint64_t* __restrict__ keys, int64_t n, int l,
+                                int32_t* __restrict__ slots)
+{
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const uint64_t key = keys[b];
+    const int32_t ci = (int32_t)compact3(key), cj = (int32_t)compact3(key >> 1),
+                  ck = (int32_t)compact3(key >> 2);
+    const int32_t lim = 1 << l;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int32_t i = ci + dx, j = cj + dy, k = ck + dz;
+                int64_t f = -1;
+                if (i >= 0 && j >= 0 && k >= 0 && i < lim && j < lim && k < lim)
+                    f = find_key(keys, n, key_of(i, j, k));
+                slots[b * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] = (int32_t)f;
+            }
+}
+
 // I(B) of level l: children (level l) of the neighbours (level l-1) of B's parent that are not
 // neighbours of B. Parents are visited in ascending index and children of a parent are
 // contiguous and ascending, so entries come out sorted by source index.
@@ -720,6 +742,16 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s)
                                    L.il_code, L.n_il, dmap, L.il_tix);
             FFMM_LAUNCH_CHECK();
         }
+        // neighbour slots of the parent levels (M2L by parent pairs) and the offset-code map
+        for (int l = 1; l < depth; ++l) {
+            LevelData& L = p->lev[l];
+            L.nb_slots = p->arena.alloc_n<int32_t>(27 * (size_t)std::max<int64_t>(L.n, 1));
+            hipLaunchKernelGGL(neighbour_slots, dim3(blocks_for(L.n, 128)), dim3(128), 0, s, L.keys, L.n,
+                               l, L.nb_slots);
+            FFMM_LAUNCH_CHECK();
+        }
+        p->code_map = p->arena.alloc_n<int32_t>(kNumCodes);
+        FFMM_HIP(hipMemcpyAsync(p->code_map, map, sizeof(map), hipMemcpyHostToDevice, s));
         FFMM_HIP(hipStreamSynchronize(s));
     } catch (...) {
         tmp.release();

@@ -118,13 +118,17 @@ def test_transfer_tables_match_oracle(gpu):
 CASES["sphere65k_d5"] = (lambda: wl.sphere_points(65536), 177 * np.sqrt(65536 / 2 ** 20), 5)
 
 
-@pytest.mark.parametrize("name", ["cube4096", "sphere6000", "sphere65k_d5"])
-def test_fp64_stages_and_matvec_match_oracle(gpu, name):
+@pytest.mark.parametrize("name,by_parent", [("cube4096", 0), ("sphere6000", 0), ("sphere65k_d5", 0),
+                                             ("cube4096", 1), ("sphere65k_d5", 1)])
+def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent):
+    """Every stage of the FP64 path against the oracle; with by_parent the M2L runs by parent
+    pairs (the same sums in another order)."""
     gen, kappa, depth = CASES[name]
     x = gen()
     q = wl.complex_normal(len(x))
-    log("fp64 stages %s" % name)
+    log("fp64 stages %s by_parent=%d" % (name, by_parent))
     p = ff.Plan(dev_points(x), kappa, 1e-6, depth=depth)
+    p.set_tuning(m2l_by_parent=by_parent)
     out = p.matvec(dev_complex(q)).cpu().numpy()
     info = p.info()
     o = OPlan(x, kappa, None, depth=info["depth"], quads=oracle_quads(p))
