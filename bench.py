@@ -43,6 +43,9 @@ def parse():
                     help="only run a plain device copy of MIB MiB five times (PMC calibration)")
     ap.add_argument("--large", action="store_true",
                     help="also run 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS")
+    ap.add_argument("--volume", action="store_true",
+                    help="also run the volume workload: 2^12..2^22 points uniform in the unit cube, "
+                         "kappa = 2 pi N^(1/3) / 2.52, FP32, eps 1e-4, automatic method and depth")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the autograd run (2^18 sphere points, kappa 88, loss sum |phi - phi_t|^2)")
@@ -255,6 +258,40 @@ def main():
         del pl
         torch.cuda.empty_cache()
 
+    volume = None
+    if args.volume:
+        # O(N) at constant points per wavelength with the time-optimal level count, and the
+        # FMM/direct crossover (the volume workload of the paper's running-time study)
+        volume = []
+        for e in (12, 14, 16, 18, 20, 22):
+            nv = 1 << e
+            kv = 2.0 * np.pi * nv ** (1.0 / 3.0) / 2.52
+            xv = wl.cube_points(nv, seed=0)
+            qv = wl.complex_normal(nv, seed=1)
+            xvt = torch.as_tensor(xv, dtype=torch.float64, device=dev)
+            qvt = torch.as_tensor(qv, dtype=torch.complex128, device=dev).to(torch.complex64)
+            t0 = time.perf_counter()
+            pv = ff.Plan(xvt, kv, 1e-4, precision="fp32", method="auto")
+            torch.cuda.synchronize()
+            sv = time.perf_counter() - t0
+            iv = pv.info()
+            msv = timed(lambda: pv.matvec(qvt), 5, 1)
+            ent = {"n": nv, "kappa": kv, "method": iv["method"], "depth": iv["depth"], "ms": msv,
+                   "value": nv / (msv * 1e-3) / 1e6, "setup_s": sv}
+            if nv <= 1 << 18:
+                pd = ff.Plan(xvt, kv, 1e-4, precision="fp32", method="direct")
+                ent["direct_ms"] = timed(lambda: pd.matvec(qvt), 3, 1)
+                del pd
+            if not args.no_cpu:
+                tv = wl.subset(nv, min(nv, 256), seed=7)
+                ov = pv.matvec(qvt).cpu().numpy().astype(np.complex128)[tv]
+                rv = direct.matvec(xv, qv, kv, targets=tv)
+                ent["rel_err"] = float(np.linalg.norm(ov - rv) / np.linalg.norm(rv))
+            log("volume: %s" % ent)
+            volume.append(ent)
+            del pv
+            torch.cuda.empty_cache()
+
     grad = None
     if not args.no_grad:
         # forward + backward of loss = sum |phi - phi_t|^2 through the differentiable matvec;
@@ -347,6 +384,7 @@ def main():
         "batched": batched,
         "large": large,
         "autograd": grad,
+        "volume": volume,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -70,7 +70,19 @@ typedef struct {
     int32_t reduce_depth;    /* with depth = 0: 1 (default) lowers the depth while the leaf level
                                 cannot reach eps (low-frequency breakdown, Section 3.5.1) */
     int32_t ell_override[FFMM_MAX_LEVELS]; /* > 0 forces ell at that level (tests); 0 = auto */
+    int32_t method;          /* ffmm_method: FFMM_METHOD_FMM (default), FFMM_METHOD_DIRECT or
+                                FFMM_METHOD_AUTO */
 } ffmm_options;
+
+/*
+ * FFMM_METHOD_DIRECT evaluates the sum over all pairs (the O(N^2) method the FMM is compared
+ * with; FP64 distance and phase as in the near field). FFMM_METHOD_AUTO times, at plan creation,
+ * the direct sum (for n <= 2^18) and the FMM at the automatic depth and its feasible neighbours
+ * (one level shallower, one deeper; a level whose leaves cannot reach eps is skipped), with
+ * max_rhs unit charges, and keeps the fastest plan: the time-optimal level count and the
+ * FMM/direct crossover of Section 4 on the caller's point set. depth must be 0 with AUTO.
+ */
+typedef enum { FFMM_METHOD_FMM = 0, FFMM_METHOD_DIRECT = 1, FFMM_METHOD_AUTO = 2 } ffmm_method;
 
 typedef struct ffmm_plan ffmm_plan; /* opaque */
 
@@ -90,6 +102,7 @@ typedef struct {
     int64_t n_near_pairs;                /* ordered source/target pairs of the near field */
     int64_t device_bytes;                /* device memory held by the plan */
     int32_t max_rhs;
+    int32_t method;                      /* FFMM_METHOD_FMM or FFMM_METHOD_DIRECT (depth 0) */
 } ffmm_plan_info;
 
 /* Fill *o with the defaults listed above. o must not be NULL. */
@@ -183,10 +196,10 @@ typedef struct {
                                    largest that does not exceed nrhs */
     int32_t rs_slab[4];         /* FP32 resample k-slab depth (16, 32 or 64) of step 1, steps 2+3,
                                    upward steps 4+5 and downward steps 4+5; default 16, 32, 32, 16 */
-    int32_t m2l_by_parent;      /* 1: M2L by parent pairs, each source signature and transfer
-                                   function read once per parent pair (pays where parents hold
-                                   many children: volume distributions); 0 (default): one target
-                                   box per block over its interaction list */
+    int32_t m2l_by_parent;      /* 1 (default): M2L by parent pairs, each source signature and
+                                   transfer function read once per parent pair (2.5x faster at the
+                                   leaves of a volume distribution, equal on surfaces); 0: one
+                                   target box per block over its interaction list */
 } ffmm_tuning;
 
 /* Fill *t with the defaults listed above. t must not be NULL. */

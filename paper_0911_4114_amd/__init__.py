@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("max_leaf_points", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("eps_safety", ctypes.c_double),
                 ("max_rhs", ctypes.c_int32), ("reduce_depth", ctypes.c_int32),
-                ("ell_override", ctypes.c_int32 * MAX_LEVELS)]
+                ("ell_override", ctypes.c_int32 * MAX_LEVELS), ("method", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -55,7 +55,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_ilist", ctypes.c_int64 * MAX_LEVELS),
                 ("predicted_err", ctypes.c_double * MAX_LEVELS),
                 ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("max_rhs", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -155,7 +155,8 @@ class Plan:
     """
 
     def __init__(self, points, kappa, eps, precision="fp64", depth=None, max_leaf=64,
-                 alpha=None, eps_safety=None, max_rhs=1, reduce_depth=True, ell_override=None):
+                 alpha=None, eps_safety=None, max_rhs=1, reduce_depth=True, ell_override=None,
+                 method="fmm"):
         lib = load_library()
         if not (isinstance(points, torch.Tensor) and points.is_cuda):
             raise TypeError("points must be a CUDA tensor")
@@ -172,6 +173,7 @@ class Plan:
         if eps_safety is not None:
             o.eps_safety = float(eps_safety)
         o.max_rhs = int(max_rhs)
+        o.method = {"fmm": 0, "direct": 1, "auto": 2}[method]
         o.reduce_depth = 1 if reduce_depth else 0
         for l, v in (ell_override or {}).items():
             o.ell_override[int(l)] = int(v)
@@ -237,6 +239,7 @@ class Plan:
             "n_boxes": list(pi.n_boxes[: d + 1]), "n_ilist": list(pi.n_ilist[: d + 1]),
             "predicted_err": list(pi.predicted_err[: d + 1]), "n_near_pairs": pi.n_near_pairs,
             "device_bytes": pi.device_bytes, "max_rhs": pi.max_rhs,
+            "method": ("fmm", "direct")[pi.method],
         }
 
     def perm(self):

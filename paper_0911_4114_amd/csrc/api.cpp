@@ -147,9 +147,101 @@ static void release_streams(ffmm_plan* p)
     p->near_stream = nullptr;
 }
 
+// FFMM_METHOD_DIRECT: the points in the caller's order and the identity permutation.
+static void build_direct(ffmm_plan* p, const double* d_points, hipStream_t s)
+{
+    p->direct = true;
+    p->depth = 0;
+    p->lev.assign(1, LevelData{});
+    p->lev[0].n = 1;
+    std::vector<int64_t> id(p->n);
+    for (int64_t i = 0; i < p->n; ++i) id[i] = i;
+    p->perm = p->arena.alloc_n<int64_t>(p->n);
+    FFMM_HIP(hipMemcpyAsync(p->perm, id.data(), sizeof(int64_t) * p->n, hipMemcpyHostToDevice, s));
+    p->xs = p->arena.alloc_n<double>(3 * p->n);
+    FFMM_HIP(hipMemcpyAsync(p->xs, d_points, sizeof(double) * 3 * p->n, hipMemcpyDeviceToDevice, s));
+    FFMM_HIP(hipStreamSynchronize(s));
+    p->near_pairs = p->n * (p->n - 1);
+}
+
 }  // namespace ffmm
 
 using namespace ffmm;
+
+// FFMM_METHOD_AUTO: build the candidate plans, time each on unit charges, keep the fastest.
+static ffmm_plan* create_fastest(const double* d_points, int64_t n, double kappa, double eps,
+                                 const ffmm_options& opt, hipStream_t s)
+{
+    std::vector<ffmm_plan*> plans;
+    DeviceArena tmp;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&](ffmm_plan* keep) {
+        for (ffmm_plan* q : plans)
+            if (q != keep) ffmm_plan_destroy(q);
+        tmp.release();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    try {
+        auto make = [&](int method, int depth) {
+            ffmm_options o = opt;
+            o.method = method;
+            o.depth = depth;
+            ffmm_plan* q = nullptr;
+            const ffmm_status st = ffmm_plan_create(d_points, n, kappa, eps, &o, s, &q);
+            if (st == FFMM_OK) plans.push_back(q);
+            else if (st != FFMM_ERR_OUT_OF_MEMORY) fail(st, g_last_error);
+            return q;
+        };
+        ffmm_plan* first = make(FFMM_METHOD_FMM, 0);
+        if (!first) fail(FFMM_ERR_OUT_OF_MEMORY, "no candidate plan fits in device memory");
+        const int d0 = first->depth;
+        const double u = opt.precision == FFMM_FP32 ? kUnitRoundoffFP32 : kUnitRoundoffFP64;
+        for (int d : {d0 - 1, d0 + 1})
+            if (d >= 2 && d <= kMaxDepth && leaf_feasible(kappa * first->side / (double)(1 << d), opt.alpha,
+                                                            eps, u))
+                make(FFMM_METHOD_FMM, d);
+        if (n <= (int64_t(1) << 18)) make(FFMM_METHOD_DIRECT, 0);
+        // unit charges for every right-hand side
+        const size_t cs = opt.precision == FFMM_FP32 ? 8 : 16;
+        const size_t cnt = (size_t)opt.max_rhs * n;
+        std::vector<char> ones(cs * cnt, 0);
+        for (size_t i = 0; i < cnt; ++i) {
+            if (cs == 8) ((float*)ones.data())[2 * i] = 1.0f;
+            else ((double*)ones.data())[2 * i] = 1.0;
+        }
+        void* dq = tmp.alloc(cs * cnt);
+        void* dout = tmp.alloc(cs * cnt);
+        FFMM_HIP(hipMemcpyAsync(dq, ones.data(), cs * cnt, hipMemcpyHostToDevice, s));
+        FFMM_HIP(hipEventCreate(&e0));
+        FFMM_HIP(hipEventCreate(&e1));
+        ffmm_plan* best = nullptr;
+        float best_ms = 1e30f;
+        for (ffmm_plan* q : plans) {
+            run_matvec(q, dq, dout, opt.max_rhs, FFMM_STAGE_ALL, false, false, s);
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                FFMM_HIP(hipEventRecord(e0, s));
+                run_matvec(q, dq, dout, opt.max_rhs, FFMM_STAGE_ALL, false, false, s);
+                FFMM_HIP(hipEventRecord(e1, s));
+                FFMM_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                FFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ms_min = std::min(ms_min, ms);
+            }
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = q;
+            }
+        }
+        cleanup(best);
+        best->opt.method = FFMM_METHOD_AUTO;
+        return best;
+    } catch (...) {
+        cleanup(nullptr);
+        throw;
+    }
+}
 
 extern "C" {
 
@@ -187,7 +279,7 @@ ffmm_status ffmm_tuning_default(ffmm_tuning* t)
     t->rs_slab[1] = 32;
     t->rs_slab[2] = 32;
     t->rs_slab[3] = 16;
-    t->m2l_by_parent = 0;
+    t->m2l_by_parent = 1;
     g_last_error.clear();
     return FFMM_OK;
 }
@@ -226,10 +318,18 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
         for (int l = 0; l < FFMM_MAX_LEVELS; ++l)
             if (opt.ell_override[l] < 0 || opt.ell_override[l] > 2000)
                 fail(FFMM_ERR_INVALID_ARG, "ell_override out of range");
+        if (opt.method != FFMM_METHOD_FMM && opt.method != FFMM_METHOD_DIRECT && opt.method != FFMM_METHOD_AUTO)
+            fail(FFMM_ERR_INVALID_ARG, "unknown method");
+        if (opt.method == FFMM_METHOD_AUTO && opt.depth != 0)
+            fail(FFMM_ERR_INVALID_ARG, "depth must be 0 with FFMM_METHOD_AUTO");
         int ndev = 0;
         FFMM_HIP(hipGetDeviceCount(&ndev));
         if (ndev < 1) fail(FFMM_ERR_HIP, "no HIP device");
         hipStream_t s = (hipStream_t)hip_stream;
+        if (opt.method == FFMM_METHOD_AUTO) {
+            *out = create_fastest(d_points, n, kappa, eps, opt, s);
+            return;
+        }
         p = new ffmm_plan();
         p->n = n;
         p->kappa = kappa;
@@ -242,9 +342,13 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
             FFMM_HIP(hipGetDevice(&dev));
             FFMM_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         }
-        build_tree(p, d_points, s);
-        build_tables(p, s);
-        prepare_rel(p, s);
+        if (opt.method == FFMM_METHOD_DIRECT) {
+            build_direct(p, d_points, s);
+        } else {
+            build_tree(p, d_points, s);
+            build_tables(p, s);
+            prepare_rel(p, s);
+        }
         allocate_workspaces(p);
         FFMM_HIP(hipStreamSynchronize(s));
         *out = p;
@@ -424,6 +528,7 @@ ffmm_status ffmm_plan_info_get(const ffmm_plan* p, ffmm_plan_info* out)
         out->n_near_pairs = p->near_pairs;
         out->device_bytes = (int64_t)p->arena.bytes;
         out->max_rhs = p->opt.max_rhs;
+        out->method = p->direct ? FFMM_METHOD_DIRECT : FFMM_METHOD_FMM;
     });
 }
 

@@ -108,6 +108,7 @@ struct Resampler {
 
 struct ffmm_plan {
     int64_t n = 0;
+    bool direct = false;            // FFMM_METHOD_DIRECT: no tree, all pairs evaluated
     double kappa = 0.0, eps = 0.0;
     ffmm_options opt{};
     int prec = FFMM_FP64;

@@ -465,6 +465,53 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __res
 // R and kappa R in FP64; in the FP32 path kappa R is reduced modulo 2 pi in FP64 and the
 // sine/cosine, 1/R and the sums are FP32.
 // ------------------------------------------------------------------------------------------
+// One near-field term of target (xi, yi, zi) and source pj (x, y, z) with charge qj: with GRAD the
+// gradient e^{i kR}(i kR - 1)/R^3 (x_i - x_j) q_j, else e^{i kR}/R q_j, added to acc. R = 0 exactly
+// (the target itself, or a coincident point) contributes nothing.
+template <class R, class C, bool GRAD>
+__device__ __forceinline__ void pair_term(double xi, double yi, double zi, double4 pj, C qj, double kappa,
+                                          double kappa_rev, C (&acc)[GRAD ? 3 : 1])
+{
+    const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const bool ok = r2 > 0.0;
+    const double r2s = ok ? r2 : 1.0;
+    R c, s, inv;
+    double rr;
+    if constexpr (sizeof(R) == 4) {
+        // y0 = hardware reciprocal square root of the FP32-rounded R^2; one Newton step in FP64
+        // written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so R and the phase
+        // kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the phase is reduced modulo 1 in
+        // FP64 before the FP32 sine/cosine, and 1/R = y0 (1 + e) needs FP32 only.
+        const float y0f = __builtin_amdgcn_rsqf((float)r2s);
+        const double y0 = (double)y0f;
+        const double u = r2s * y0;
+        const double eh = fma(-0.5, u * y0, 0.5);
+        rr = fma(u, eh, u);
+        double rev = rr * kappa_rev;
+        rev -= floor(rev);
+        cis((float)rev, c, s);
+        inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
+    } else {
+        rr = sqrt(r2s);
+        cis(kappa * rr, c, s);
+        inv = ok ? 1.0 / rr : 0.0;
+    }
+    if constexpr (GRAD) {
+        const R kr = (R)(kappa * rr);
+        const R inv3 = inv * inv * inv;
+        const R gr = (-c - s * kr) * inv3, gi = (c * kr - s) * inv3;
+        const C gq = cmul(cmk<C>(gr, gi), qj);
+        const R d[3] = {(R)dx, (R)dy, (R)dz};
+        for (int a = 0; a < 3; ++a) {
+            acc[a].x += d[a] * gq.x;
+            acc[a].y += d[a] * gq.y;
+        }
+    } else {
+        cmac(acc[0], cmk<C>(c * inv, s * inv), qj);
+    }
+}
+
 template <class R, class C, bool GRAD>
 __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restrict__ xs,
                                                     const C* __restrict__ q,
@@ -529,50 +576,7 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
                 }
                 wave_lds_sync();
                 if (!valid) continue;
-                for (int t = sub; t < ns; t += g) {
-                    const double4 pj = sp[t];
-                    const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    // R = 0 exactly for the target itself (and for coincident points): excluded
-                    const bool ok = r2 > 0.0;
-                    const double r2s = ok ? r2 : 1.0;
-                    R c, s, inv;
-                    double rr;
-                    if constexpr (sizeof(R) == 4) {
-                        // y0 = hardware reciprocal square root of the FP32-rounded R^2; one Newton
-                        // step in FP64 written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so
-                        // R and the phase kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the
-                        // phase is reduced modulo 1 in FP64 before the FP32 sine/cosine, and
-                        // 1/R = y0 (1 + e) needs FP32 only.
-                        const float y0f = __builtin_amdgcn_rsqf((float)r2s);
-                        const double y0 = (double)y0f;
-                        const double u = r2s * y0;
-                        const double eh = fma(-0.5, u * y0, 0.5);
-                        rr = fma(u, eh, u);
-                        double rev = rr * kappa_rev;
-                        rev -= floor(rev);
-                        cis((float)rev, c, s);
-                        inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
-                    } else {
-                        rr = sqrt(r2s);
-                        cis(kappa * rr, c, s);
-                        inv = ok ? 1.0 / rr : 0.0;
-                    }
-                    if (GRAD) {
-                        // e^{i kR}(i kR - 1)/R^3 (x_i - x_j)
-                        const R kr = (R)(kappa * rr);
-                        const R inv3 = inv * inv * inv;
-                        const R gr = (-c - s * kr) * inv3, gi = (c * kr - s) * inv3;
-                        const C gq = cmul(cmk<C>(gr, gi), sq[t]);
-                        const R d[3] = {(R)dx, (R)dy, (R)dz};
-                        for (int a = 0; a < 3; ++a) {
-                            acc[a].x += d[a] * gq.x;
-                            acc[a].y += d[a] * gq.y;
-                        }
-                    } else {
-                        cmac(acc[0], cmk<C>(c * inv, s * inv), sq[t]);
-                    }
-                }
+                for (int t = sub; t < ns; t += g) pair_term<R, C, GRAD>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
             }
         }
         // combine the g partial sums of every target
@@ -590,6 +594,53 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
         wave_lds_sync();
     }
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Direct sum over all pairs (the O(N^2) evaluation of eqn. HelmholtzMatrixVector the FMM is
+// measured against), with the near-field arithmetic. A block: 64 targets (one per lane of each
+// wave); the four waves take interleaved quarters of every 256-source tile staged in LDS, and
+// their partial sums are added at the end.
+// ------------------------------------------------------------------------------------------
+template <class R, class C, bool GRAD>
+__global__ __launch_bounds__(256) void direct_kernel(const double* __restrict__ xs, const C* __restrict__ q,
+                                                     int64_t n, double kappa, C* __restrict__ out)
+{
+    constexpr int NC = GRAD ? 3 : 1;
+    __shared__ double4 sp[256];
+    __shared__ C sq[256];
+    __shared__ C part[4][NC][kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int64_t r = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+    const bool valid = i < n;
+    const int64_t ii = valid ? i : 0;
+    const double xi = xs[3 * ii], yi = xs[3 * ii + 1], zi = xs[3 * ii + 2];
+    const double kappa_rev = kappa / kTwoPi;
+    C acc[NC];
+    for (int a = 0; a < NC; ++a) acc[a] = cz<C>();
+    for (int64_t s0 = 0; s0 < n; s0 += 256) {
+        const int ns = (int)min<int64_t>(256, n - s0);
+        __syncthreads();
+        if (tid < ns) {
+            const int64_t j = s0 + tid;
+            sp[tid] = make_double4(xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], 0.0);
+            sq[tid] = q[r * n + j];
+        }
+        __syncthreads();
+        for (int t = wv; t < ns; t += 4) pair_term<R, C, GRAD>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+    }
+    for (int a = 0; a < NC; ++a) part[wv][a][lane] = acc[a];
+    __syncthreads();
+    if (wv == 0 && valid)
+        for (int a = 0; a < NC; ++a) {
+            C v = part[0][a][lane];
+            for (int u = 1; u < 4; ++u) {
+                v.x += part[u][a][lane].x;
+                v.y += part[u][a][lane].y;
+            }
+            out[(r * n + i) * NC + a] = v;
+        }
 }
 
 // coordinates relative to the leaf centre, in the plan precision
@@ -623,6 +674,25 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         hipLaunchKernelGGL(gather_q<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)qv,
                            p->perm, n, conj_io ? 1 : 0, qs);
         FFMM_LAUNCH_CHECK();
+    }
+    if (p->direct) {
+        // all pairs are near: one direct-sum launch, then the scatter
+        if (stages & FFMM_STAGE_NEAR) {
+            StageScope sc(p, FFMM_PROF_P2P, s);
+            if (gradient)
+                hipLaunchKernelGGL((direct_kernel<R, C, true>), dim3(nblk(n, kWave), nrhs), dim3(256), 0, s,
+                                   p->xs, qs, n, p->kappa, phin);
+            else
+                hipLaunchKernelGGL((direct_kernel<R, C, false>), dim3(nblk(n, kWave), nrhs), dim3(256), 0, s,
+                                   p->xs, qs, n, p->kappa, phin);
+            FFMM_LAUNCH_CHECK();
+        }
+        StageScope sc(p, FFMM_PROF_SCATTER, s);
+        hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)nullptr,
+                           (stages & FFMM_STAGE_NEAR) ? (const C*)phin : (const C*)nullptr, p->perm, n,
+                           width, conj_io ? 1 : 0, (C*)outv);
+        FFMM_LAUNCH_CHECK();
+        return;
     }
     // P2P needs only the gathered charges: it runs on the plan's near-field stream
     const bool fork = (stages & FFMM_STAGE_NEAR) && p->tune.near_stream;

@@ -34,7 +34,7 @@ def test_options_default_and_status_strings():
     assert o.struct_size == ctypes.sizeof(ff.Options)
     assert o.precision == 0 and o.max_leaf_points == 64 and o.depth == 0
     assert abs(o.alpha - 0.8) < 1e-15 and abs(o.eps_safety - 0.1) < 1e-15
-    assert o.max_rhs == 1 and o.reduce_depth == 1
+    assert o.max_rhs == 1 and o.reduce_depth == 1 and o.method == 0
     assert lib.ffmm_options_default(None) == -1
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.ffmm_status_string(code)
@@ -46,7 +46,7 @@ def test_tuning_default_and_null_plan():
     assert lib.ffmm_tuning_default(ctypes.byref(t)) == 0
     assert t.struct_size == ctypes.sizeof(ff.Tuning)
     assert (t.near_stream, t.p2p_blocks_per_cu, t.m2l_rhs_block) == (1, 0, 0)
-    assert list(t.rs_slab) == [16, 32, 32, 16] and t.m2l_by_parent == 0
+    assert list(t.rs_slab) == [16, 32, 32, 16] and t.m2l_by_parent == 1
     assert lib.ffmm_tuning_default(None) == -1
     assert lib.ffmm_plan_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.ffmm_plan_get_tuning(None, ctypes.byref(t)) == -1
@@ -93,6 +93,15 @@ def test_plan_create_rejects_bad_arguments():
     o.max_rhs = 0
     assert _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))[0] == -1
     o.max_rhs = 1
+    o.method = 3
+    st, msg = _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))
+    assert st == -1 and "method" in msg
+    o.method = 2
+    o.depth = 4
+    st, msg = _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))
+    assert st == -1 and "AUTO" in msg
+    o.method = 0
+    o.depth = 0
     o.struct_size = 4
     assert _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))[0] == -1
 

@@ -113,7 +113,7 @@ def test_launch_configurations_agree_and_autotune(setup):
     for cfg, tol in (({"m2l_rhs_block": 1}, 1e-6), ({"m2l_rhs_block": 2}, 1e-6),
                      ({"rs_slab": [64, 64, 64, 64]}, 1e-6), ({"rs_slab": [16, 16, 16, 16]}, 1e-6),
                      ({"m2l_by_parent": 1, "m2l_rhs_block": 2}, 1e-5),
-                     ({"m2l_by_parent": 1, "m2l_rhs_block": 1}, 1e-5), ({"m2l_by_parent": 0}, 1e-6)):
+                     ({"m2l_by_parent": 1, "m2l_rhs_block": 1}, 1e-5), ({"m2l_by_parent": 0}, 1e-5)):
         p.set_tuning(**cfg)
         got = p.matvec(q).cpu().numpy()
         assert rel_l2(got, base) < tol, (cfg, rel_l2(got, base))
@@ -131,3 +131,32 @@ def test_launch_configurations_agree_and_autotune(setup):
     tg = wl.subset(n, 300)
     ref = direct.matvec(x, Q[2], KAPPA, targets=tg)
     assert rel_l2(got[2][tg], ref) < 1e-4
+
+
+def test_direct_method_and_automatic_choice(setup):
+    """The all-pairs method equals the oracle's direct sum (FP64 to rounding, FP32 to its
+    near-field accuracy), including the adjoint and the field gradient; the automatic method
+    keeps one of its candidates and meets eps."""
+    x, xt = setup
+    n = 3000
+    x = x[:n]
+    xt = dev_points(x)
+    kappa = 30.0
+    q = wl.complex_normal(n, seed=12)
+    ref = direct.matvec(x, q, kappa)
+    pd = ff.Plan(xt, kappa, 1e-6, method="direct")
+    assert pd.info()["method"] == "direct" and pd.info()["depth"] == 0
+    assert rel_l2(pd.matvec(dev_complex(q)).cpu().numpy(), ref) < 1e-13
+    g = wl.complex_normal(n, seed=13)
+    adj = pd.adjoint(dev_complex(g)).cpu().numpy()
+    assert rel_l2(adj, np.conj(direct.matvec(x, np.conj(g), kappa))) < 1e-13
+    fg = pd.field_gradient(dev_complex(q)).cpu().numpy()
+    assert rel_l2(fg, direct.gradient(x, q, kappa)) < 1e-12
+    assert np.array_equal(pd.perm(), np.arange(n))
+    p32 = ff.Plan(xt, kappa, 1e-4, precision="fp32", method="direct")
+    assert rel_l2(p32.matvec(dev_complex(q, True)).cpu().numpy(), ref) < 1e-6
+    pa = ff.Plan(xt, kappa, 1e-4, precision="fp32", method="auto")
+    info = pa.info()
+    log("auto method: %s depth %d" % (info["method"], info["depth"]))
+    assert info["method"] in ("fmm", "direct")
+    assert rel_l2(pa.matvec(dev_complex(q, True)).cpu().numpy(), ref) < 1e-4
