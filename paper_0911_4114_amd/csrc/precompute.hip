@@ -205,6 +205,164 @@ int32_t* upload_int(DeviceArena& a, const std::vector<int>& v, hipStream_t s)
     return d;
 }
 
+// The real matrix B of the BMTF theta step: T^{s,L}(theta_n) = sum_j B[n][j] T(theta'_j), with
+//   B[n][j] = Re sum_{|k|<=kmax} e^{i k theta_n} sum_{|p|<=ell} s_{k-p} e^{-i p theta'_j} / nt,
+// theta'_j = 2 pi j / nt (nt = 2 ell + 1 samples of T), theta_n = 2 pi n / N_theta, kmax =
+// N_theta/2 - 1, s the |sin| coefficients (Section 3.2, Alg. BMTF). Two O(ell^3) contractions,
+// on the device: C[k][j] = sum_p s_{k-p} e^{-i p theta'_j}, then B.
+__global__ void bmtf_conv(int ell, int kmax, const double2* __restrict__ tw, double2* __restrict__ C)
+{
+    const int nt = 2 * ell + 1;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)(2 * kmax + 1) * nt) return;
+    const int j = (int)(idx % nt);
+    const int k = (int)(idx / nt) - kmax;
+    double re = 0.0, im = 0.0;
+    for (int pp = -ell; pp <= ell; ++pp) {
+        const long d = (long)k - pp;
+        if (d % 2 != 0) continue;
+        const double sk = 2.0 / (kPi * (1.0 - (double)d * (double)d));
+        long t = ((long)pp * j) % nt;
+        if (t < 0) t += nt;
+        const double2 w = tw[t];
+        re += sk * w.x;
+        im += sk * w.y;
+    }
+    C[idx] = make_double2(re, im);
+}
+
+__global__ void bmtf_rows(int nt, int kmax, int rows, int ntheta, const double2* __restrict__ tw2,
+                          const double2* __restrict__ C, double* __restrict__ B)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)rows * nt) return;
+    const int j = (int)(idx % nt);
+    const int n = (int)(idx / nt);
+    double acc = 0.0;
+    for (int k = -kmax; k <= kmax; ++k) {
+        long t = ((long)k * n) % ntheta;
+        if (t < 0) t += ntheta;
+        const double2 e = tw2[t], c = C[(int64_t)(k + kmax) * nt + j];
+        acc += e.x * c.x - e.y * c.y;
+    }
+    B[idx] = acc / nt;
+}
+
+// B of (ell, ntheta) in device memory of arena a
+double* bmtf_theta_matrix(DeviceArena& a, int ell, int ntheta, hipStream_t s)
+{
+    const int nt = 2 * ell + 1, kmax = ntheta / 2 - 1, rows = ntheta / 2 + 1;
+    std::vector<cd> tw(nt), tw2(ntheta);
+    for (int t = 0; t < nt; ++t) tw[t] = std::exp(cd(0.0, -2.0 * kPi * (double)t / nt));
+    for (int t = 0; t < ntheta; ++t) tw2[t] = std::exp(cd(0.0, 2.0 * kPi * (double)t / ntheta));
+    double2* dtw = a.alloc_n<double2>(nt);
+    double2* dtw2 = a.alloc_n<double2>(ntheta);
+    FFMM_HIP(hipMemcpyAsync(dtw, tw.data(), sizeof(double2) * nt, hipMemcpyHostToDevice, s));
+    FFMM_HIP(hipMemcpyAsync(dtw2, tw2.data(), sizeof(double2) * ntheta, hipMemcpyHostToDevice, s));
+    double2* C = a.alloc_n<double2>((size_t)(2 * kmax + 1) * nt);
+    double* B = a.alloc_n<double>((size_t)rows * nt);
+    hipLaunchKernelGGL(bmtf_conv, dim3(nblk((int64_t)(2 * kmax + 1) * nt, 256)), dim3(256), 0, s, ell, kmax,
+                       dtw, C);
+    FFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bmtf_rows, dim3(nblk((int64_t)rows * nt, 256)), dim3(256), 0, s, nt, kmax, rows,
+                       ntheta, dtw2, C, B);
+    FFMM_LAUNCH_CHECK();
+    FFMM_HIP(hipStreamSynchronize(s));   // the host twiddle vectors go out of scope
+    return B;
+}
+
+// Alg. Nphi error sums: out[n][c] = sum_{|p|<=ell} |Cf_n,p| |J_{M(N,p)}(ka r sin theta_n)| for
+// N = 4 (c + 1), M(N, p) = N - |p| if |p| < N/2 else |p| (eqn. EpsIPhi's aliasing index).
+__global__ void nphi_error(int rows, int ell, int ncols, int ncand, int emax,
+                           const double2* __restrict__ Cf, const double* __restrict__ E,
+                           double* __restrict__ out)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)rows * ncand) return;
+    const int c = (int)(idx % ncand), n = (int)(idx / ncand);
+    const int np = 4 * (c + 1);
+    const double2* cf = Cf + (int64_t)n * (ncols - 1) + (ncols / 2 - 1);
+    const double* e = E + (int64_t)n * (emax + 1);
+    double acc = 0.0;
+    for (int pp = -ell; pp <= ell; ++pp) {
+        const int ap = pp < 0 ? -pp : pp;
+        const int m = (ap < np / 2) ? np - ap : ap;
+        acc += hypot(cf[pp].x, cf[pp].y) * e[m];
+    }
+    out[idx] = acc;
+}
+
+// Alg. Nphi with the band-limited transfer function of r0 = |r0| x (box units) computed on the
+// device by the BMTF kernels (the same quantities the host search forms with O(ell^3) DFTs).
+void select_nphi_device(double ka, double r, double r0, int ell, int ntheta, double eps,
+                        const double* dB, int* nphi, hipStream_t s)
+{
+    const int rows = ntheta / 2 + 1, nt = 2 * ell + 1;
+    const int ncols = 4 * ((2 * ell + 2 + 3) / 4);
+    const int nphi_max = 4 * ((2 * ell + 2 + 64 + 3) / 4);
+    const int ncand = nphi_max / 4;
+    DeviceArena tmp;
+    try {
+        std::vector<double> jn(ell + 1), yn(ell + 1);
+        sph_bessel_j(ell, ka * r0, jn.data());
+        sph_bessel_y(ell, ka * r0, yn.data());
+        std::vector<cd> cn(ell + 1);
+        cd ipow(1.0, 0.0);
+        for (int n = 0; n <= ell; ++n) {
+            cn[n] = cd(0.0, ka / (4.0 * kPi)) * ipow * (2.0 * n + 1.0) * cd(jn[n], yn[n]);
+            ipow *= cd(0.0, 1.0);
+        }
+        const double xhat[3] = {1.0, 0.0, 0.0};
+        double2* dcn = tmp.alloc_n<double2>(ell + 1);
+        double* dr0 = tmp.alloc_n<double>(3);
+        FFMM_HIP(hipMemcpyAsync(dcn, cn.data(), sizeof(double2) * (ell + 1), hipMemcpyHostToDevice, s));
+        FFMM_HIP(hipMemcpyAsync(dr0, xhat, sizeof(xhat), hipMemcpyHostToDevice, s));
+        double2* A = tmp.alloc_n<double2>((size_t)nt * ncols);
+        double2* TL = tmp.alloc_n<double2>((size_t)rows * ncols);
+        double2* Cf = tmp.alloc_n<double2>((size_t)rows * (ncols - 1));
+        std::vector<cd> tw(ncols);
+        for (int t = 0; t < ncols; ++t) tw[t] = std::exp(cd(0.0, -2.0 * kPi * t / ncols));
+        double2* dtw = tmp.alloc_n<double2>(ncols);
+        FFMM_HIP(hipMemcpyAsync(dtw, tw.data(), sizeof(double2) * ncols, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(bmtf_sample, dim3(nblk((int64_t)nt * ncols, 256)), dim3(256), 0, s, 1, ell, ncols,
+                           dcn, dr0, A);
+        FFMM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(bmtf_theta, dim3(nblk((int64_t)rows * ncols, 256)), dim3(256), 0, s, 1, nt, rows,
+                           ncols, dB, A, TL);
+        FFMM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(bmtf_phi_coef, dim3(nblk((int64_t)rows * (ncols - 1), 256)), dim3(256), 0, s, 1,
+                           rows, ncols, dtw, TL, Cf);
+        FFMM_LAUNCH_CHECK();
+        // |J_m(ka r sin theta_n)|, m = 0..nphi_max, per row
+        std::vector<double> E((size_t)rows * (nphi_max + 1));
+        for (int n = 0; n < rows; ++n)
+            bessel_j_abs(nphi_max, ka * r * std::fabs(std::sin(2.0 * kPi * n / ntheta)),
+                         &E[(size_t)n * (nphi_max + 1)]);
+        double* dE = tmp.alloc_n<double>(E.size());
+        FFMM_HIP(hipMemcpyAsync(dE, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, s));
+        double* dout = tmp.alloc_n<double>((size_t)rows * ncand);
+        hipLaunchKernelGGL(nphi_error, dim3(nblk((int64_t)rows * ncand, 256)), dim3(256), 0, s, rows, ell,
+                           ncols, ncand, nphi_max, Cf, dE, dout);
+        FFMM_LAUNCH_CHECK();
+        std::vector<double> err((size_t)rows * ncand);
+        FFMM_HIP(hipMemcpyAsync(err.data(), dout, sizeof(double) * err.size(), hipMemcpyDeviceToHost, s));
+        FFMM_HIP(hipStreamSynchronize(s));
+        const double tol = eps / (4.0 * kPi * kPi);
+        std::vector<int> out(rows, nphi_max);
+        for (int n = 0; n < rows; ++n)
+            for (int c = 0; c < ncand; ++c)
+                if (err[(size_t)n * ncand + c] < tol) {
+                    out[n] = 4 * (c + 1);
+                    break;
+                }
+        for (int n = 0; n < rows; ++n) nphi[n] = std::max(out[n], out[rows - 1 - n]);
+    } catch (...) {
+        tmp.release();
+        throw;
+    }
+    tmp.release();
+}
+
 // Transfer tables of one level, FP64 on the device, stored in precision R.
 template <class R>
 void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
@@ -212,35 +370,9 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
     const int ell = L.par.ell, ntheta = L.par.ntheta, rows = L.nrows, K = L.K;
     const int nt = 2 * ell + 1;
     const int ncols = 4 * ((2 * ell + 2 + 3) / 4);
-    const int kmax = ntheta / 2 - 1;
-    // B[n][j] = Re sum_{|k|<=kmax} e^{i k theta_n} sum_{|p|<=ell} s_{k-p} e^{-i p theta'_j} / nt
-    std::vector<cd> C((size_t)(2 * kmax + 1) * nt);
-    std::vector<cd> ep(nt * (size_t)(2 * ell + 1));
-    for (int pp = -ell; pp <= ell; ++pp)
-        for (int j = 0; j < nt; ++j) {
-            long t = ((long)pp * j) % nt;
-            ep[(size_t)(pp + ell) * nt + j] = std::exp(cd(0.0, -2.0 * kPi * (double)t / nt));
-        }
-    for (int k = -kmax; k <= kmax; ++k)
-        for (int pp = -ell; pp <= ell; ++pp) {
-            double sk = sin_abs_coeff(k - pp);
-            if (sk == 0.0) continue;
-            cd* crow = &C[(size_t)(k + kmax) * nt];
-            const cd* e = &ep[(size_t)(pp + ell) * nt];
-            for (int j = 0; j < nt; ++j) crow[j] += sk * e[j];
-        }
-    std::vector<double> B((size_t)rows * nt, 0.0);
-    for (int n = 0; n < rows; ++n)
-        for (int k = -kmax; k <= kmax; ++k) {
-            long t = ((long)k * n) % ntheta;
-            cd e = std::exp(cd(0.0, 2.0 * kPi * (double)t / ntheta));
-            const cd* crow = &C[(size_t)(k + kmax) * nt];
-            for (int j = 0; j < nt; ++j) B[(size_t)n * nt + j] += (e * crow[j]).real() / nt;
-        }
     DeviceArena tmp;
     try {
-        double* dB = tmp.alloc_n<double>(B.size());
-        FFMM_HIP(hipMemcpy(dB, B.data(), sizeof(double) * B.size(), hipMemcpyHostToDevice));
+        const double* dB = bmtf_theta_matrix(tmp, ell, ntheta, s);
         std::vector<int> row_of_k(K);
         for (int n = 0; n < rows; ++n)
             for (int k = L.row_off[n]; k < L.row_off[n + 1]; ++k) row_of_k[k] = n;
@@ -405,7 +537,31 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
         LevelData& L = p->lev[l];
         const double ka = p->kappa * L.a;
         const int ell_in = (l < FFMM_MAX_LEVELS) ? p->opt.ell_override[l] : 0;
-        level_params(ka, p->opt.alpha, p->opt.eps_safety * p->eps, u, ell_in, &L.par);
+        {
+            // ell and N_theta on the host (O(ell^2)); the O(ell^3) N_phi search on the device
+            LevelParams& lp = L.par;
+            const double eps_l = p->opt.eps_safety * p->eps;
+            const double r = p->opt.alpha * std::sqrt(3.0), r0 = 2.0;
+            if (ell_in > 0) {
+                lp.ell = ell_in;
+                std::vector<double> tot(ell_in + 1);
+                predicted_error(ka, r, r0, ell_in, u, tot.data());
+                lp.predicted = tot[ell_in];
+            } else {
+                lp.ell = select_ell(ka, r, r0, eps_l, u, &lp.predicted);
+            }
+            lp.ntheta = select_ntheta(ka, r, r0, lp.ell, eps_l);
+            lp.nphi.assign(lp.ntheta / 2 + 1, 4);
+            DeviceArena bt;
+            try {
+                const double* dB = bmtf_theta_matrix(bt, lp.ell, lp.ntheta, s);
+                select_nphi_device(ka, r, r0, lp.ell, lp.ntheta, eps_l, dB, lp.nphi.data(), s);
+            } catch (...) {
+                bt.release();
+                throw;
+            }
+            bt.release();
+        }
         p->predicted[l] = L.par.predicted;
         L.nrows = L.par.ntheta / 2 + 1;
         L.row_off.assign(L.nrows + 1, 0);
