@@ -173,7 +173,8 @@ enum {
 
 /*
  * Stage timing. With on = 1 every later matvec-type call records a pair of HIP events around
- * each stage on its stream (a small overhead); ffmm_profile_read waits for them, returns the
+ * each stage on its stream (a small overhead) and runs P2P on the calling stream, after the far
+ * field, so that no two stages overlap; ffmm_profile_read waits for them, returns the
  * accumulated milliseconds ms[FFMM_PROF_NUM] and launch counts calls[FFMM_PROF_NUM] since the
  * last read (either may be NULL), and resets the accumulators.
  */

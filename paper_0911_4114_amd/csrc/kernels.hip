@@ -533,11 +533,17 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
     const double kappa_rev = kappa / kTwoPi;
     // A block serves logical blocks of kWpb leaves in a loop (the grid may hold fewer blocks than
     // there are leaves, so that P2P leaves room for the far-field kernels running beside it). With
-    // a grid of whole XCD rounds each XCD walks a contiguous Morton range.
+    // one block per logical block, or a grid of whole XCD rounds, each XCD walks a contiguous
+    // Morton range, so that the neighbour boxes a leaf reads are mostly in its XCD's L2 already.
     const unsigned nlog = (unsigned)((nleaf + kWpb - 1) / kWpb);
     constexpr unsigned kXcd = 8;
     unsigned j0, jstep, jend, base;
-    if (gridDim.x % kXcd == 0) {
+    if (gridDim.x == nlog) {
+        base = xcd_block(blockIdx.x, nlog);
+        j0 = 0;
+        jend = 1;
+        jstep = 1;
+    } else if (gridDim.x % kXcd == 0) {
         const unsigned x = blockIdx.x % kXcd, per = nlog / kXcd, rem = nlog % kXcd;
         base = x * per + min(x, rem);
         jend = per + (x < rem ? 1 : 0);
@@ -694,8 +700,9 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         FFMM_LAUNCH_CHECK();
         return;
     }
-    // P2P needs only the gathered charges: it runs on the plan's near-field stream
-    const bool fork = (stages & FFMM_STAGE_NEAR) && p->tune.near_stream;
+    // P2P needs only the gathered charges: it runs on the plan's near-field stream (not while
+    // stages are timed: each stage's event interval then holds its own kernels alone)
+    const bool fork = (stages & FFMM_STAGE_NEAR) && p->tune.near_stream && !p->profile;
     auto launch_p2p = [&](hipStream_t sn) {
         StageScope sc(p, FFMM_PROF_P2P, sn);
         const int64_t nl = p->lev[L].n;

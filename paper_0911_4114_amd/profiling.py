@@ -2,13 +2,17 @@
 
 ``python -m paper_0911_4114_amd.profiling trace <results.db|kernel_trace.csv> [top]`` prints a
 per-kernel Markdown table (calls, total and average duration).
+``python -m paper_0911_4114_amd.profiling streams <kernel_trace.csv> <kernel>`` prints, for one
+kernel (short name), its calls and average duration per HIP stream.
 ``python -m paper_0911_4114_amd.profiling pmc <counter_collection.csv> <kernel substring> <counter>``
 prints the mean of a counter over the dispatches of the matching kernels.
 ``python -m paper_0911_4114_amd.profiling traffic --kernel NAME --fetch CSV --write CSV
 --copy-fetch CSV --copy-write CSV --copy-bytes B --source FILE`` prints the HBM-traffic summary
 of one kernel (its largest launches): FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what
 the same counter reads for a plain device copy of B bytes, plus the SHA-256 of the kernel's source
-file, so that a reader can tell whether the figures still describe the code."""
+file, so that a reader can tell whether the figures still describe the code. With ``--family`` the
+kernel name is a prefix and the figures are the mean over every dispatch of every matching kernel
+(a stage launched once per tree level, at several grid sizes)."""
 import argparse
 import csv
 import collections
@@ -41,6 +45,15 @@ def trace_rows(path, top=25):
     return rows[:top]
 
 
+def stream_rows(path, kernel):
+    """(stream id, calls, average_us) of the kernel whose short name equals ``kernel``."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if short_name(r["Kernel_Name"]) == kernel:
+            agg[int(r["Stream_Id"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return [(sid, len(v), sum(v) / len(v)) for sid, v in sorted(agg.items())]
+
+
 def pmc_mean(path, kernel, counter):
     """Mean of a PMC counter (rocprofv3 --pmc CSV) over dispatches whose name contains kernel."""
     vals = collections.defaultdict(float)
@@ -50,14 +63,16 @@ def pmc_mean(path, kernel, counter):
     return sum(vals.values()) / max(len(vals), 1), len(vals)
 
 
-def counter_per_dispatch(path, counter, kernel=None, largest=True):
+def counter_per_dispatch(path, counter, kernel=None, largest=True, family=False):
     """Mean counter value (summed over its instances) per dispatch of the kernel whose short name
-    equals ``kernel`` (any kernel if None), over the dispatches with the largest grid."""
+    equals ``kernel`` (any kernel if None; with ``family``, every kernel whose short name starts
+    with it), over the dispatches with the largest grid (over all of them if not ``largest``)."""
     vals, grid = collections.defaultdict(float), {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        if kernel is not None and short_name(r["Kernel_Name"]) != kernel:
+        name = short_name(r["Kernel_Name"])
+        if kernel is not None and not (name.startswith(kernel) if family else name == kernel):
             continue
         vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
         grid[r["Dispatch_Id"]] = int(r["Grid_Size"])
@@ -75,12 +90,12 @@ def file_sha256(path):
 def traffic_summary(a):
     cf, _, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
     cw, _, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
-    f, nf, gf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
-    w, nw, gw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    f, nf, gf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, not a.family, a.family)
+    w, nw, gw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, not a.family, a.family)
     fs, ws = a.copy_bytes / (cf * 1024.0), a.copy_bytes / (cw * 1024.0)
     lines = [
-        "kernel: %s" % a.kernel,
-        "grid_size: %d" % gf,
+        "kernel: %s" % (a.kernel + "*" if a.family else a.kernel),
+        "grid_size: %s" % ("all" if a.family else "%d" % gf),
         "source: %s" % a.source,
         "source_sha256: %s" % file_sha256(a.source),
         "fetch_kib_per_dispatch: %.1f (%d dispatches)" % (f, nf),
@@ -125,9 +140,16 @@ if __name__ == "__main__":
         ap.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer",
                         help="short name of the copy kernel (a device-to-device tensor copy)")
         ap.add_argument("--source", required=True)
+        ap.add_argument("--family", action="store_true",
+                        help="--kernel is a name prefix; average over all matching dispatches")
         print(traffic_summary(ap.parse_args(sys.argv[2:])))
     elif sys.argv[1] == "trace":
         main(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25)
+    elif sys.argv[1] == "streams":
+        print("| stream | calls | average (us) |")
+        print("|---|---|---|")
+        for sid, calls, avg in stream_rows(sys.argv[2], sys.argv[3]):
+            print("| %d | %d | %.1f |" % (sid, calls, avg))
     elif sys.argv[1] == "pmc":
         m, cnt = pmc_mean(sys.argv[2], sys.argv[3], sys.argv[4])
         print("%s %s: mean %.1f over %d dispatches" % (sys.argv[3], sys.argv[4], m, cnt))
