@@ -93,6 +93,9 @@ __device__ inline unsigned xcd_block(unsigned b, unsigned nblocks)
 // operations in order, so a fence at wavefront scope (which also stops the compiler moving memory
 // operations across it) is the whole synchronisation.
 constexpr int kWpb = 4;
+
+// Largest near-field phase range, in revolutions, for which P2P takes its FP32 phase form.
+constexpr double kFastRev = 8.0;
 __device__ inline void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -467,38 +470,52 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __res
 // ------------------------------------------------------------------------------------------
 // One near-field term of target (xi, yi, zi) and source pj (x, y, z) with charge qj: with GRAD the
 // gradient e^{i kR}(i kR - 1)/R^3 (x_i - x_j) q_j, else e^{i kR}/R q_j, added to acc. R = 0 exactly
-// (the target itself, or a coincident point) contributes nothing.
-template <class R, class C, bool GRAD>
+// (the target itself, or a coincident point) contributes nothing. The coordinate differences and
+// R^2 are FP64 always: close pairs lose their digits to cancellation otherwise.
+// FAST (FP32 only, for near-field ranges of at most kFastRev revolutions of the phase): R^2 is
+// rounded to FP32 and 1/R, R and the phase kR/2pi follow in FP32, relative error ~1e-7, so the
+// phase is good to ~1e-6 of a revolution.
+template <class R, class C, bool GRAD, bool FAST = false>
 __device__ __forceinline__ void pair_term(double xi, double yi, double zi, double4 pj, C qj, double kappa,
                                           double kappa_rev, C (&acc)[GRAD ? 3 : 1])
 {
     const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool ok = r2 > 0.0;
-    const double r2s = ok ? r2 : 1.0;
-    R c, s, inv;
-    double rr;
-    if constexpr (sizeof(R) == 4) {
+    R c, s, inv, kr;
+    if constexpr (FAST) {
+        static_assert(sizeof(R) == 4, "FAST is an FP32 form");
+        const float r2f = (float)r2;
+        const bool ok = r2f > 0.0f;
+        const float y = __builtin_amdgcn_rsqf(ok ? r2f : 1.0f);
+        const float rf = r2f * y;
+        cis(rf * (float)kappa_rev, c, s);
+        inv = ok ? y : 0.0f;
+        if constexpr (GRAD) kr = (float)kappa * rf;
+    } else if constexpr (sizeof(R) == 4) {
         // y0 = hardware reciprocal square root of the FP32-rounded R^2; one Newton step in FP64
         // written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so R and the phase
         // kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the phase is reduced modulo 1 in
         // FP64 before the FP32 sine/cosine, and 1/R = y0 (1 + e) needs FP32 only.
+        const bool ok = r2 > 0.0;
+        const double r2s = ok ? r2 : 1.0;
         const float y0f = __builtin_amdgcn_rsqf((float)r2s);
         const double y0 = (double)y0f;
         const double u = r2s * y0;
         const double eh = fma(-0.5, u * y0, 0.5);
-        rr = fma(u, eh, u);
+        const double rr = fma(u, eh, u);
         double rev = rr * kappa_rev;
         rev -= floor(rev);
         cis((float)rev, c, s);
         inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
+        if constexpr (GRAD) kr = (R)(kappa * rr);
     } else {
-        rr = sqrt(r2s);
+        const bool ok = r2 > 0.0;
+        const double rr = sqrt(ok ? r2 : 1.0);
         cis(kappa * rr, c, s);
         inv = ok ? 1.0 / rr : 0.0;
+        if constexpr (GRAD) kr = kappa * rr;
     }
     if constexpr (GRAD) {
-        const R kr = (R)(kappa * rr);
         const R inv3 = inv * inv * inv;
         const R gr = (-c - s * kr) * inv3, gi = (c * kr - s) * inv3;
         const C gq = cmul(cmk<C>(gr, gi), qj);
@@ -512,7 +529,7 @@ __device__ __forceinline__ void pair_term(double xi, double yi, double zi, doubl
     }
 }
 
-template <class R, class C, bool GRAD>
+template <class R, class C, bool GRAD, bool FAST>
 __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restrict__ xs,
                                                     const C* __restrict__ q,
                                                     const int32_t* __restrict__ start,
@@ -525,7 +542,7 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
     __shared__ double4 spa[kWpb][kWave];   // staged sources: x, y, z (w unused)
     __shared__ C sqa[kWpb][kWave];
     __shared__ C parta[kWpb][NC][kWave];
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
     double4* sp = spa[wv];
     C* sq = sqa[wv];
     C (*part)[kWave] = parta[wv];
@@ -581,8 +598,16 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
                     sq[lane] = q[r * n + j];
                 }
                 wave_lds_sync();
-                if (!valid) continue;
-                for (int t = sub; t < ns; t += g) pair_term<R, C, GRAD>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+                if (g == 1) {
+                    // one target per lane: a loop the whole wave runs in step (lanes past the
+                    // chunk repeat its first target and store nothing)
+#pragma unroll 4
+                    for (int t = 0; t < ns; ++t)
+                        pair_term<R, C, GRAD, FAST>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+                } else if (valid) {
+                    for (int t = sub; t < ns; t += g)
+                        pair_term<R, C, GRAD, FAST>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+                }
             }
         }
         // combine the g partial sums of every target
@@ -709,14 +734,17 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         const int64_t nlog = (nl + kWpb - 1) / kWpb;
         const int bpc = p->tune.p2p_blocks_per_cu;
         const unsigned grid = (unsigned)(bpc > 0 ? std::min<int64_t>(nlog, (int64_t)p->n_cu * bpc) : nlog);
+        // FP32 phase when the near-field range spans few revolutions (sources within two leaf
+        // sides per axis: R <= 2 sqrt(3) a)
+        const bool fast = sizeof(R) == 4 && p->kappa * 2.0 * std::sqrt(3.0) * p->lev[L].a / kTwoPi <= kFastRev;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn, p->xs, qs, p->leaf_start,
+                               p->leaf_count, p->nb_ptr, p->nb_src, p->kappa, phin, n, (int64_t)nl);
+        };
         if (gradient)
-            hipLaunchKernelGGL((p2p_kernel<R, C, true>), dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn,
-                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phin, n, (int64_t)nl);
+            fast ? go(p2p_kernel<R, C, true, (sizeof(R) == 4)>) : go(p2p_kernel<R, C, true, false>);
         else
-            hipLaunchKernelGGL((p2p_kernel<R, C, false>), dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn,
-                               p->xs, qs, p->leaf_start, p->leaf_count, p->nb_ptr, p->nb_src, p->kappa,
-                               phin, n, (int64_t)nl);
+            fast ? go(p2p_kernel<R, C, false, (sizeof(R) == 4)>) : go(p2p_kernel<R, C, false, false>);
         FFMM_LAUNCH_CHECK();
     };
     if (fork && !(stages & FFMM_STAGE_FAR)) {

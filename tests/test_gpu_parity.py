@@ -155,6 +155,32 @@ def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent):
     assert rel_l2(out, full) < 1e-6
 
 
+@pytest.mark.parametrize("kappa,depth", [(40.0, None), (200.0, 2)])
+def test_fp32_near_field_matches_oracle(gpu, kappa, depth):
+    """FP32 P2P against the oracle's FP64 near field, per point relative to the sum of the term
+    magnitudes sum_j |q_j| / R_ij. kappa 40 on the default tree keeps the near-field phase under
+    8 revolutions (the FP32-phase form); kappa 200 at depth 2 spans ~55 (the FP64-phase form),
+    with leaves of over 64 points (several target chunks per leaf)."""
+    x = wl.sphere_points(6000)
+    q = wl.complex_normal(len(x)).astype(np.complex64).astype(complex)
+    p = ff.Plan(dev_points(x), kappa, 1e-4, precision="fp32", depth=depth, reduce_depth=False)
+    info = p.info()
+    a_leaf = info["root_side"] / 2 ** info["depth"]
+    log("fp32 near kappa %g depth %d range %.1f rev" % (kappa, info["depth"],
+                                                         kappa * 2 * np.sqrt(3) * a_leaf / (2 * np.pi)))
+    near = p.matvec_stages(dev_complex(q, fp32=True), ff.STAGE_NEAR).cpu().numpy().astype(complex)
+    o = OPlan(x, kappa, None, depth=info["depth"], quads=oracle_quads(p))
+    qs = q[o.tree.perm]
+    ref = np.empty(len(x), complex)
+    ref[o.tree.perm] = o.p2p(qs)
+    o.kappa = 0.0                     # sum_j |q_j| / R_ij over the same near pairs
+    amp = np.empty(len(x))
+    amp[o.tree.perm] = o.p2p(np.abs(qs)).real
+    err = np.abs(near - ref) / amp
+    log("  max err / amplitude %.3e, rel l2 %.3e" % (err.max(), rel_l2(near, ref)))
+    assert err.max() < 3e-5 and rel_l2(near, ref) < 1e-5
+
+
 def test_fp32_matvec_meets_eps(gpu):
     x = wl.sphere_points(20000)
     q = wl.complex_normal(len(x))
