@@ -276,7 +276,9 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
                                                    C* __restrict__ out, int64_t nb, int nrhs)
 {
     // per occupied neighbour P' of P (compacted): D, first child, octant mask of its children;
-    // the transfer-table index of each of its 27 child-offset differences
+    // per (P', child-offset difference e): the transfer-table index and, in bits 16..23, the
+    // target octants whose pair at that offset is present on both sides; -1 where there is no
+    // such pair or the offset is a near-field one
     __shared__ int32_t s_d[27], s_sb[27], s_sm[27], s_tx[27][27];
     __shared__ int32_t s_n, s_tmask;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
@@ -286,30 +288,48 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
     const int k = kvalid ? kraw : K - 1;   // tail lanes compute on a valid direction, store nothing
     const int r0 = blockIdx.y * RB;
     const int tb = child_start[P], tn = child_count[P];
-    if (threadIdx.x == 0) {
-        int n = 0, tm = 0;
-        for (int i = 0; i < tn; ++i) tm |= 1 << octant[tb + i];
-        for (int D = 0; D < 27; ++D) {
-            const int Pn = pslots[P * 27 + D];
-            if (Pn < 0) continue;
-            const int sb = child_start[Pn], sn = child_count[Pn];
-            int sm = 0;
+    if (threadIdx.x < kWave) {
+        // wave 0: lane D reads neighbour slot D (compacted by a ballot); lanes < tn read the
+        // octants of P's own children
+        const int D = threadIdx.x;
+        const int Pn = D < 27 ? pslots[P * 27 + D] : -1;
+        int sb = 0, sm = 0;
+        if (Pn >= 0) {
+            sb = child_start[Pn];
+            const int sn = child_count[Pn];
             for (int i = 0; i < sn; ++i) sm |= 1 << octant[sb + i];
-            s_d[n] = D;
-            s_sb[n] = sb;
-            s_sm[n] = sm;
-            ++n;
         }
-        s_n = n;
-        s_tmask = tm;
+        const uint64_t occ = __ballot(Pn >= 0);
+        if (Pn >= 0) {
+            const int pos = __popcll(occ & ((1ull << D) - 1));
+            s_d[pos] = D;
+            s_sb[pos] = sb;
+            s_sm[pos] = sm;
+        }
+        const int ot = D < tn ? octant[tb + D] : -1;
+        int tm = 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) tm |= (__ballot(ot == o) != 0 ? 1 : 0) << o;
+        if (D == 0) {
+            s_n = __popcll(occ);
+            s_tmask = tm;
+        }
     }
     __syncthreads();
-    const int nn = s_n;
+    const int nn = s_n, tmask = s_tmask;
     for (int t = threadIdx.x; t < nn * 27; t += 256) {
         const int i = t / 27, e = t % 27, D = s_d[i];
-        const int code = (2 * (D % 3 - 1) + e % 3 - 1 + 3) + 7 * (2 * ((D / 3) % 3 - 1) + (e / 3) % 3 - 1 + 3) +
-                         49 * (2 * (D / 9 - 1) + e / 9 - 1 + 3);
-        s_tx[i][e] = code_map[code];
+        const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+        const int code = (2 * (D % 3 - 1) + ex + 3) + 7 * (2 * ((D / 3) % 3 - 1) + ey + 3) +
+                         49 * (2 * (D / 9 - 1) + ez + 3);
+        int tx = code_map[code];
+        int pairs = 0;
+        for (int ot = 0; ot < 8; ++ot) {
+            const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
+            if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
+            pairs |= ((tmask >> ot) & (s_sm[i] >> (ax + 2 * ay + 4 * az)) & 1) << ot;
+        }
+        s_tx[i][e] = (pairs && tx >= 0) ? (pairs << 16) | tx : -1;
     }
     __syncthreads();
     const int64_t plane = nb * (int64_t)K;
@@ -317,7 +337,6 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
     int kp[kNumSym];
 #pragma unroll
     for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[g * K + k];
-    const int tmask = s_tmask;
     C acc[8][RB];
 #pragma unroll
     for (int o = 0; o < 8; ++o)
@@ -325,31 +344,24 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
         for (int q = 0; q < RB; ++q) acc[o][q] = cz<C>();
     for (int i = 0; i < nn; ++i) {
         const int sb = s_sb[i], smask = s_sm[i];
-        // source signatures of the occupied octants
+        // source signatures of the present octants (absent ones read the first child's address
+        // and are never used)
         C ms[8][RB];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
-            if (!((smask >> o) & 1)) continue;
-            const int ci = sb + __builtin_popcount(smask & ((1 << o) - 1));
+            const bool present = (smask >> o) & 1;
+            const int ci = sb + (present ? __builtin_popcount(smask & ((1 << o) - 1)) : 0);
             const C* mp = M + (int64_t)r0 * plane + (uint64_t)(uint32_t)ci * (uint32_t)K + k;
 #pragma unroll
-            for (int q = 0; q < RB; ++q) ms[o][q] = (q < nr) ? mp[(int64_t)q * plane] : cz<C>();
+            for (int q = 0; q < RB; ++q) ms[o][q] = mp[(int64_t)(q < nr ? q : 0) * plane];
         }
 #pragma unroll
         for (int e = 0; e < 27; ++e) {
-            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
-            // octant pairs (ot, ot + e) present on both sides
-            int pairs = 0;
-#pragma unroll
-            for (int ot = 0; ot < 8; ++ot) {
-                const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
-                if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
-                pairs |= ((tmask >> ot) & (smask >> (ax + 2 * ay + 4 * az)) & 1) << ot;
-            }
-            if (!pairs) continue;
-            const int tx = __builtin_amdgcn_readfirstlane(s_tx[i][e]);
-            if (tx < 0) continue;   // a neighbour of the target: near field
+            const int v = __builtin_amdgcn_readfirstlane(s_tx[i][e]);
+            if (v < 0) continue;
+            const int tx = v & 0xffff, pairs = v >> 16;
             const C tv = T[(uint64_t)(uint32_t)(tx >> 4) * (uint32_t)K + kp[tx & (kNumSym - 1)]];
+            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
 #pragma unroll
             for (int ot = 0; ot < 8; ++ot) {
                 const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
