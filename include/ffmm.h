@@ -64,7 +64,8 @@ typedef struct {
                                 many points (default 64); ignored when depth > 0 */
     int32_t depth;           /* 0 = automatic; otherwise the leaf level L, 2 <= L <= 21 */
     double alpha;            /* representative |r| = alpha sqrt(3) a_l, Section 3.3.3
-                                (default 0.8) */
+                                (default 0.8); levels with kappa a_l > 100 use alpha = 1 (the
+                                box diagonal) wherever some ell reaches eps there */
     double eps_safety;       /* per-level tolerance = eps_safety * eps (default 0.1) */
     int32_t max_rhs;         /* largest nrhs of a later call; sizes the workspaces (default 1) */
     int32_t reduce_depth;    /* with depth = 0: 1 (default) lowers the depth while the leaf level
@@ -240,7 +241,8 @@ const char* ffmm_last_error_message(void);
 
 /*
  * Host-only parameter choice for one level in box units (no GPU needed): ka = kappa a_l,
- * |r| = alpha sqrt(3), |r0| = 2 (Section 3.3.3). ell from the Gegenbauer truncation error of
+ * |r| = alpha' sqrt(3), |r0| = 2 (Section 3.3.3), alpha' = alpha, or 1 when ka > 100 and some
+ * ell reaches eps at |r| = sqrt(3). ell from the Gegenbauer truncation error of
  * eqn. eps_G plus the low-frequency rounding floor of the given precision (Section 2.1), N_theta
  * by Alg. Ntheta, N_phi(theta_n) by Alg. Nphi (Section 3.3).
  *   ell_in      : > 0 to force ell, 0 to choose it.

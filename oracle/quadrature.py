@@ -187,9 +187,30 @@ def select_nphi(ka, r, r0, ell, ntheta, eps):
     return np.maximum(out, out[::-1])
 
 
+# Above this box size in wavelength units (ka) the design radius widens to the box diagonal.
+WIDE_KA = 100.0
+
+
+def design_alpha(ka, alpha, eps, u=UNIT_ROUNDOFF["fp64"]):
+    """The representative |r| = alpha sqrt(3) of Section 3.3.3 for one level. The paper's alpha
+    (0.8) stands for the typical pair of interacting points; pairs near opposite corners reach
+    |r| = sqrt(3). The truncation rule places ell just past ka|r| (Section 2.1), so for large ka
+    an ell chosen at 0.8 sqrt(3) leaves those pairs short of it, and their error exceeds eps. So
+    for ka > WIDE_KA the full diagonal (alpha = 1) is used whenever some ell reaches eps there;
+    otherwise (and for alpha >= 1 as given) alpha is kept."""
+    if not ka > WIDE_KA or alpha >= 1.0:
+        return alpha
+    r = np.sqrt(3.0)
+    emax = ell_search_max(ka, r)
+    tot = gegenbauer_error(ka, r, 2.0, emax) + rounding_floor(ka, 2.0, emax, u)
+    return 1.0 if np.any(tot[1:] < eps) else alpha
+
+
 def level_quadrature(ka, alpha, eps, ell=None, u=UNIT_ROUNDOFF["fp64"]):
     """Full parameter choice for one level in box units (Sections 2.1, 3.3):
-    |r| = alpha sqrt(3), |r0| = 2. Returns (LevelQuad, info dict with the predicted error)."""
+    |r| = design_alpha(...) sqrt(3), |r0| = 2. Returns (LevelQuad, info dict with the predicted
+    error and the design alpha)."""
+    alpha = design_alpha(ka, alpha, eps, u)
     r = alpha * np.sqrt(3.0)
     r0 = 2.0
     if ell is None:
@@ -199,4 +220,4 @@ def level_quadrature(ka, alpha, eps, ell=None, u=UNIT_ROUNDOFF["fp64"]):
     nth = select_ntheta(ka, r, r0, ell, eps)
     nphi = select_nphi(ka, r, r0, ell, nth, eps)
     q = LevelQuad(ell, nth, nphi)
-    return q, {"predicted": eg, "ka": ka}
+    return q, {"predicted": eg, "ka": ka, "alpha": alpha}

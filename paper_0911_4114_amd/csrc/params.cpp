@@ -307,9 +307,26 @@ void select_nphi(double ka, double r, double r0, int ell, int ntheta, double eps
     for (int n = 0; n < rows; ++n) nphi[n] = std::max(out[n], out[rows - 1 - n]);
 }
 
+// The representative |r| = alpha sqrt(3) of Section 3.3.3 for one level. The paper's alpha (0.8)
+// stands for the typical pair of interacting points; pairs near opposite corners reach |r| =
+// sqrt(3). The truncation rule places ell just past ka|r| (Section 2.1), so for large ka an ell
+// chosen at 0.8 sqrt(3) leaves those pairs short of it and their error exceeds eps: above kWideKa
+// the full diagonal (alpha = 1) is used whenever some ell reaches eps there.
+double design_alpha(double ka, double alpha, double eps, double u)
+{
+    if (!(ka > kWideKa) || alpha >= 1.0) return alpha;
+    const double r = std::sqrt(3.0);
+    const int emax = ell_search_max(ka, r);
+    std::vector<double> tot(emax + 1);
+    predicted_error(ka, r, 2.0, emax, u, tot.data());
+    for (int l = 1; l <= emax; ++l)
+        if (tot[l] < eps) return 1.0;
+    return alpha;
+}
+
 void level_params(double ka, double alpha, double eps, double u, int ell_in, LevelParams* lp)
 {
-    const double r = alpha * std::sqrt(3.0), r0 = 2.0;
+    const double r = design_alpha(ka, alpha, eps, u) * std::sqrt(3.0), r0 = 2.0;
     if (ell_in > 0) {
         lp->ell = ell_in;
         int emax = std::max(ell_in, 1);

@@ -541,7 +541,7 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             // ell and N_theta on the host (O(ell^2)); the O(ell^3) N_phi search on the device
             LevelParams& lp = L.par;
             const double eps_l = p->opt.eps_safety * p->eps;
-            const double r = p->opt.alpha * std::sqrt(3.0), r0 = 2.0;
+            const double r = design_alpha(ka, p->opt.alpha, eps_l, u) * std::sqrt(3.0), r0 = 2.0;
             if (ell_in > 0) {
                 lp.ell = ell_in;
                 std::vector<double> tot(ell_in + 1);

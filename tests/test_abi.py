@@ -63,6 +63,17 @@ def test_host_parameter_choice_matches_oracle(ka, eps, prec):
     assert abs(pred - info["predicted"]) <= 1e-3 * info["predicted"] + 1e-14
 
 
+@pytest.mark.parametrize("ka,eps,prec", [(110.0, 1e-4, 1)])
+def test_host_parameter_choice_matches_oracle_wide(ka, eps, prec):
+    """Above ka = 100 the design radius becomes the box diagonal where eps is reachable there."""
+    ell, nth, nphi, pred = ff.select_level_params(ka, 0.8, eps, prec)
+    u = UNIT_ROUNDOFF["fp32" if prec else "fp64"]
+    q, info = level_quadrature(ka, 0.8, eps, u=u)
+    assert (ell, nth) == (q.ell, q.ntheta) and nphi == list(q.nphi)
+    assert abs(pred - info["predicted"]) <= 1e-3 * info["predicted"] + 1e-14
+    assert info["alpha"] in (0.8, 1.0)
+
+
 def _create(points_ptr, n, kappa, eps, opts=None):
     lib = ff.load_library()
     h = ctypes.c_void_p()

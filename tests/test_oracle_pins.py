@@ -237,3 +237,23 @@ def test_bmtf_spectral_equals_real_space():
     small[nth - b:] = c2[nbig - b:]
     real_space = np.fft.ifft(small, axis=0) * nth
     assert np.allclose(spectral, real_space, atol=1e-11 * np.abs(spectral).max())
+
+
+def test_design_radius_widens_above_ka_100():
+    """Section 2.1 puts ell just past ka|r|. At ka = 200 the ell chosen for the paper's
+    |r| = 0.8 sqrt(3) leaves the Gegenbauer truncation error at the box diagonal |r| = sqrt(3)
+    (pairs near opposite corners) above 1, where the widened choice meets eps; so the design
+    radius becomes the diagonal above ka = 100 where eps is reachable there, and stays 0.8 sqrt(3)
+    below it and where the diagonal cannot reach eps."""
+    ka, eps = 200.0, 1e-5
+    l08, _ = quadrature.select_ell(ka, 0.8 * np.sqrt(3.0), 2.0, eps)
+    l10, _ = quadrature.select_ell(ka, np.sqrt(3.0), 2.0, eps)
+    g = quadrature.gegenbauer_error(ka, np.sqrt(3.0), 2.0, l10)
+    assert l10 > l08 and g[l08] > 1.0 and g[l10] < eps
+    assert quadrature.design_alpha(ka, 0.8, eps) == 1.0
+    assert quadrature.design_alpha(100.0, 0.8, eps) == 0.8
+    assert quadrature.design_alpha(20.0, 0.8, eps) == 0.8
+    assert quadrature.design_alpha(120.0, 0.8, 1e-9) == 0.8      # out of reach at the diagonal
+    assert quadrature.design_alpha(150.0, 0.5, 1e-5) == 1.0
+    q, info = quadrature.level_quadrature(ka, 0.8, eps)
+    assert info["alpha"] == 1.0 and q.ell == l10
