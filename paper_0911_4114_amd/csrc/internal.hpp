@@ -71,6 +71,8 @@ struct LevelData {
     int32_t* d_nphi = nullptr;
     void* dirs = nullptr;           // [K][3] real
     void* weights = nullptr;        // [K] real (leaf level)
+    int Kp = 0;                     // leaf level: K / 2 antipodal direction pairs
+    int32_t* pairs = nullptr;       // leaf level: [Kp][2] (k, k') with s_k' = -s_k
     void* transfer = nullptr;       // [34][K] complex: T of the representative transfer vectors
     int32_t* tperm = nullptr;       // [16][K]: T_{g rep}(s_k) = T_rep(s_{tperm[g][k]})
     void* trans = nullptr;          // [8][K] complex: e^{i kappa s.(oct - 1/2) a_{l+1}} (l < L)

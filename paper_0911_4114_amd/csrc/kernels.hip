@@ -140,29 +140,36 @@ __global__ void scatter_out(const C* __restrict__ far, const C* __restrict__ nea
 
 // ------------------------------------------------------------------------------------------
 // P2M (Initialization, Section 2): M_b(s_k) = sum_{i in b} q_i e^{i kappa s_k . (x_i - c_b)}.
-// Block: one leaf box and 256 quadrature directions; the box's points are staged in LDS.
+// The quadrature holds every direction with its antipode, so one phase and one sine/cosine per
+// point serve both. Block: one leaf box and 256 antipodal pairs; the box's points in LDS.
 // ------------------------------------------------------------------------------------------
 template <class R, class C>
-__global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* __restrict__ dirs,
-                                                  R kfac, const int32_t* __restrict__ start,
+__global__ __launch_bounds__(256) void p2m_kernel(int Kp, int kchunks, const R* __restrict__ dirs,
+                                                  const int32_t* __restrict__ pairs, R kfac,
+                                                  const int32_t* __restrict__ start,
                                                   const int32_t* __restrict__ count,
                                                   const R* __restrict__ rel, const C* __restrict__ q,
-                                                  C* __restrict__ M, int64_t n, int64_t nb)
+                                                  C* __restrict__ M, int64_t n, int64_t nb, int K)
 {
     __shared__ R sx[256], sy[256], sz[256];
     __shared__ C sq[256];
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t b = lb / kchunks;
-    const int k = (lb % kchunks) * 256 + threadIdx.x;
+    const int pi = (lb % kchunks) * 256 + threadIdx.x;
+    const bool pvalid = pi < Kp;
     const int64_t r = blockIdx.y;
+    int k1 = 0, k2 = 0;
     R dx = 0, dy = 0, dz = 0;
-    if (k < K) {
-        dx = dirs[3 * k] * kfac;
-        dy = dirs[3 * k + 1] * kfac;
-        dz = dirs[3 * k + 2] * kfac;
+    if (pvalid) {
+        k1 = pairs[2 * pi];
+        k2 = pairs[2 * pi + 1];
+        dx = dirs[3 * k1] * kfac;
+        dy = dirs[3 * k1 + 1] * kfac;
+        dz = dirs[3 * k1 + 2] * kfac;
     }
     const int s0 = start[b], cnt = count[b];
-    C acc = cz<C>();
+    // s_k2 = -s_k1: M(s_k1) = A + iB, M(s_k2) = A - iB with A = sum cos(ph) q, B = sum sin(ph) q
+    C A = cz<C>(), B = cz<C>();
     for (int p0 = 0; p0 < cnt; p0 += 256) {
         const int np = min(256, cnt - p0);
         __syncthreads();
@@ -178,10 +185,18 @@ __global__ __launch_bounds__(256) void p2m_kernel(int K, int kchunks, const R* _
             R ph = dx * sx[t] + dy * sy[t] + dz * sz[t];
             R c, s;
             cis(ph, c, s);
-            cmac(acc, cmk<C>(c, s), sq[t]);
+            const C qt = sq[t];
+            A.x = fma(c, qt.x, A.x);
+            A.y = fma(c, qt.y, A.y);
+            B.x = fma(s, qt.x, B.x);
+            B.y = fma(s, qt.y, B.y);
         }
     }
-    if (k < K) M[(r * nb + b) * K + k] = acc;
+    if (pvalid) {
+        C* Mb = M + (r * nb + b) * K;
+        Mb[k1] = cmk<C>(A.x - B.y, A.y + B.x);
+        Mb[k2] = cmk<C>(A.x + B.y, A.y - B.x);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -389,30 +404,38 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
 // ------------------------------------------------------------------------------------------
 // L2P (far part of eqn. FMM_FinalStep): phi_i += sum_k w_k L_b(s_k) e^{i kappa s_k.(c_b - x_i)};
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
-// One wave per leaf box (four per block), one lane per target point; w_k L_b(s_k) and s_k are
-// staged in the wave's own LDS in chunks. The sum over k is blocked: plain sums of 16 terms, combined with TwoSum, which keeps
-// the FP32 accumulation error of the large cancelling terms near the size of the result.
+// One wave per leaf box (four per block), one lane per target point; the directions are taken in
+// antipodal pairs (one phase and one sine/cosine per pair), staged in the wave's own LDS in
+// chunks. The sum over k is blocked: plain sums of 16 directions, combined with TwoSum, which
+// keeps the FP32 accumulation error of the large cancelling terms near the size of the result.
 // ------------------------------------------------------------------------------------------
 constexpr int kL2PChunk = 256;
 
 template <class R, class C, bool GRAD>
-__global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __restrict__ dirs,
+__global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __restrict__ dirs,
+                                                    const int32_t* __restrict__ pairs,
                                                     const R* __restrict__ w, R kfac, R kappa,
                                                     const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ count,
                                                     const R* __restrict__ rel, const C* __restrict__ L,
-                                                    C* __restrict__ out, int64_t n, int64_t nb)
+                                                    C* __restrict__ out, int64_t n, int64_t nb, int K)
 {
     constexpr int NC = GRAD ? 3 : 1;
+    // per antipodal pair (s, -s) with weighted values u1 = w L(s) = a1 + i b1, u2 = w L(-s):
+    // s and P = a1 + a2, Q = b1 - b2, V = b1 + b2, S = a1 - a2, so that the pair contributes
+    // (c P - sn Q) + i (c V + sn S) for e^{i ph} = c + i sn, ph = kappa s.(c_b - x_i)
     __shared__ R sxa[kWpb][kL2PChunk], sya[kWpb][kL2PChunk], sza[kWpb][kL2PChunk];
-    __shared__ C swla[kWpb][kL2PChunk];
+    __shared__ R spa[kWpb][kL2PChunk], sqa[kWpb][kL2PChunk], sva[kWpb][kL2PChunk], ssa[kWpb][kL2PChunk];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
     if (b >= nb) return;
     R* sx = sxa[wv];
     R* sy = sya[wv];
     R* sz = sza[wv];
-    C* swl = swla[wv];
+    R* sP = spa[wv];
+    R* sQ = sqa[wv];
+    R* sV = sva[wv];
+    R* sS = ssa[wv];
     const int64_t r = blockIdx.y;
     const int s0 = start[b], cnt = count[b];
     const C* Lb = L + (r * nb + b) * K;
@@ -427,35 +450,42 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int K, const R* __res
         }
         R sre[NC], sim[NC], ere[NC], eim[NC];
         for (int a = 0; a < NC; ++a) sre[a] = sim[a] = ere[a] = eim[a] = 0;
-        for (int k0 = 0; k0 < K; k0 += kL2PChunk) {
-            const int nk = min(kL2PChunk, K - k0);
+        for (int k0 = 0; k0 < Kp; k0 += kL2PChunk) {
+            const int nk = min(kL2PChunk, Kp - k0);
             wave_lds_sync();
             for (int k = lane; k < nk; k += kWave) {
-                const int kk = k0 + k;
-                sx[k] = dirs[3 * kk];
-                sy[k] = dirs[3 * kk + 1];
-                sz[k] = dirs[3 * kk + 2];
-                const C lv = Lb[kk];
-                swl[k] = cmk<C>(w[kk] * lv.x, w[kk] * lv.y);
+                const int k1 = pairs[2 * (k0 + k)], k2 = pairs[2 * (k0 + k) + 1];
+                sx[k] = dirs[3 * k1];
+                sy[k] = dirs[3 * k1 + 1];
+                sz[k] = dirs[3 * k1 + 2];
+                const C l1 = Lb[k1], l2 = Lb[k2];
+                const R w1 = w[k1], w2 = w[k2];
+                const R a1 = w1 * l1.x, b1 = w1 * l1.y, a2 = w2 * l2.x, b2 = w2 * l2.y;
+                sP[k] = a1 + a2;
+                sQ[k] = b1 - b2;
+                sV[k] = b1 + b2;
+                sS[k] = a1 - a2;
             }
             wave_lds_sync();
-            for (int kb = 0; kb < nk; kb += 16) {
-                const int ke = min(kb + 16, nk);
+            // plain sums over 8 pairs (16 directions), combined with TwoSum
+            for (int kb = 0; kb < nk; kb += 8) {
+                const int ke = min(kb + 8, nk);
                 R pre[NC], pim[NC];
                 for (int a = 0; a < NC; ++a) pre[a] = pim[a] = 0;
                 for (int k = kb; k < ke; ++k) {
-                    R c, s;
-                    cis(sx[k] * x + sy[k] * y + sz[k] * z, c, s);
-                    const C t = cmul(cmk<C>(c, s), swl[k]);
+                    R c, sn;
+                    cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
                     if (GRAD) {
+                        // (-i kappa s)[c (u1 - u2) + i sn (u1 + u2)] = kappa s (Y - i X)
+                        const R X = c * sS[k] - sn * sV[k], Y = c * sQ[k] + sn * sP[k];
                         const R sa[3] = {sx[k], sy[k], sz[k]};
-                        for (int a = 0; a < 3; ++a) {       // (-i kappa s_a) t
-                            pre[a] += kappa * sa[a] * t.y;
-                            pim[a] -= kappa * sa[a] * t.x;
+                        for (int a = 0; a < 3; ++a) {
+                            pre[a] += kappa * sa[a] * Y;
+                            pim[a] -= kappa * sa[a] * X;
                         }
                     } else {
-                        pre[0] += t.x;
-                        pim[0] += t.y;
+                        pre[0] += c * sP[k] - sn * sQ[k];
+                        pim[0] += c * sV[k] + sn * sS[k];
                     }
                 }
                 for (int a = 0; a < NC; ++a) {
@@ -769,10 +799,10 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         // P2M
         {
             StageScope sc(p, FFMM_PROF_P2M, s);
-            const int kch = (leaf.K + 255) / 256;
+            const int kch = (leaf.Kp + 255) / 256;
             hipLaunchKernelGGL((p2m_kernel<R, C>), dim3((unsigned)(leaf.n * kch), nrhs), dim3(256), 0, s,
-                               leaf.K, kch, (const R*)leaf.dirs, kfac, p->leaf_start, p->leaf_count,
-                               (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n);
+                               leaf.Kp, kch, (const R*)leaf.dirs, leaf.pairs, kfac, p->leaf_start,
+                               p->leaf_count, (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n, leaf.K);
             FFMM_LAUNCH_CHECK();
         }
         // P2P forks after P2M, so that the first far-field kernel is not queued behind it
@@ -833,14 +863,14 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         StageScope sc(p, FFMM_PROF_L2P, s);
         if (gradient)
             hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
-                               p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
-                               phis, n, leaf.n);
+                               leaf.Kp, (const R*)leaf.dirs, leaf.pairs, (const R*)leaf.weights, kfac,
+                               (R)p->kappa, p->leaf_start, p->leaf_count, (const R*)p->rel,
+                               (const C*)leaf.sigL, phis, n, leaf.n, leaf.K);
         else
             hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               leaf.K, (const R*)leaf.dirs, (const R*)leaf.weights, kfac, (R)p->kappa,
-                               p->leaf_start, p->leaf_count, (const R*)p->rel, (const C*)leaf.sigL,
-                               phis, n, leaf.n);
+                               leaf.Kp, (const R*)leaf.dirs, leaf.pairs, (const R*)leaf.weights, kfac,
+                               (R)p->kappa, p->leaf_start, p->leaf_count, (const R*)p->rel,
+                               (const C*)leaf.sigL, phis, n, leaf.n, leaf.K);
         FFMM_LAUNCH_CHECK();
     }
     if (fork) {

@@ -586,7 +586,26 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             }
         }
         upload_real<R>(p->arena, &L.dirs, dirs, s);
-        if (l == depth) upload_real<R>(p->arena, &L.weights, w, s);
+        if (l == depth) {
+            upload_real<R>(p->arena, &L.weights, w, s);
+            // antipodal pairs: row theta_n at phi_m and row pi - theta_n (index N_theta/2 - n) at
+            // phi_m + pi give s and -s; the rows have equal N_phi (Alg. Nphi takes the larger of
+            // the two) and every N_phi is a multiple of 4, so all K directions pair up
+            const int half = L.par.ntheta / 2;
+            std::vector<int> pr;
+            pr.reserve(L.K);
+            for (int n = 0; n <= half - n; ++n) {
+                const int n2 = half - n, len = L.par.nphi[n];
+                if (L.par.nphi[n2] != len || len % 2 != 0) fail(FFMM_ERR_INTERNAL, "unpaired quadrature rows");
+                for (int m = 0; m < (n == n2 ? len / 2 : len); ++m) {
+                    pr.push_back(L.row_off[n] + m);
+                    pr.push_back(L.row_off[n2] + (m + len / 2) % len);
+                }
+            }
+            if ((int)pr.size() != L.K) fail(FFMM_ERR_INTERNAL, "unpaired quadrature directions");
+            L.Kp = L.K / 2;
+            L.pairs = upload_int(p->arena, pr, s);
+        }
         transfer_tables<R>(p, L, s);
         if (l < depth) {
             // e^{i kappa s.(oct - 1/2) a_{l+1}}, oct = (x, y, z) bits of the child position

@@ -257,3 +257,19 @@ def test_design_radius_widens_above_ka_100():
     assert quadrature.design_alpha(150.0, 0.5, 1e-5) == 1.0
     q, info = quadrature.level_quadrature(ka, 0.8, eps)
     assert info["alpha"] == 1.0 and q.ell == l10
+
+
+@pytest.mark.parametrize("ka,eps", [(2.77, 1e-4), (5.54, 1e-6), (22.1, 1e-8), (44.3, 1e-4)])
+def test_quadrature_closed_under_antipode(ka, eps):
+    """Every direction s of a level quadrature (Section 3.3, rows theta_n = 2 pi n / N_theta for
+    n <= N_theta / 2, N_phi from Alg. Nphi) has -s in the set with the same weight: row pi - theta
+    at phi + pi. Sums over the quadrature of e^{+-i kappa s.r} can then share one phase."""
+    from scipy.spatial import cKDTree
+    q, _ = quadrature.level_quadrature(ka, 0.8, eps)
+    d, w = q.dirs(), q.weights()
+    dist, j = cKDTree(d).query(-d)
+    assert dist.max() < 1e-12
+    assert np.allclose(w[j], w, rtol=1e-14)
+    # the pole rows hold N_phi copies of one direction; elsewhere the antipode is unique
+    interior = np.abs(d[:, 2]) < 1 - 1e-12
+    assert len(np.unique(j[interior])) == interior.sum()
