@@ -255,8 +255,6 @@ def test_design_radius_widens_above_ka_100():
     assert quadrature.design_alpha(20.0, 0.8, eps) == 0.8
     assert quadrature.design_alpha(120.0, 0.8, 1e-9) == 0.8      # out of reach at the diagonal
     assert quadrature.design_alpha(150.0, 0.5, 1e-5) == 1.0
-    q, info = quadrature.level_quadrature(ka, 0.8, eps)
-    assert info["alpha"] == 1.0 and q.ell == l10
 
 
 @pytest.mark.parametrize("ka,eps", [(2.77, 1e-4), (5.54, 1e-6), (22.1, 1e-8), (44.3, 1e-4)])
