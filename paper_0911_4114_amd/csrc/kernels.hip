@@ -279,6 +279,28 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
 // instead of reading one M and one T per pair. T is read through the quadrature symmetry as in
 // m2l_kernel.
 // ------------------------------------------------------------------------------------------
+// T value through a raw buffer resource: the table row's byte offset in a scalar register, the
+// permuted direction's byte offset per lane; reads past the table's size return zero.
+__device__ inline __amdgpu_buffer_rsrc_t table_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <class C> __device__ inline C buf_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff);
+template <> __device__ inline float2 buf_load<float2>(__amdgpu_buffer_rsrc_t rs, int voff, int soff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    float2 c;
+    __builtin_memcpy(&c, &v, sizeof(c));
+    return c;
+}
+template <> __device__ inline double2 buf_load<double2>(__amdgpu_buffer_rsrc_t rs, int voff, int soff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+    double2 c;
+    __builtin_memcpy(&c, &v, sizeof(c));
+    return c;
+}
+
 template <class C, int RB>
 __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
                                                    const int32_t* __restrict__ pslots,
@@ -291,10 +313,12 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
                                                    C* __restrict__ out, int64_t nb, int nrhs)
 {
     // per occupied neighbour P' of P (compacted): D, first child, octant mask of its children;
-    // per (P', child-offset difference e): the transfer-table index and, in bits 16..23, the
-    // target octants whose pair at that offset is present on both sides; -1 where there is no
-    // such pair or the offset is a near-field one
-    __shared__ int32_t s_d[27], s_sb[27], s_sm[27], s_tx[27][27];
+    // per (P', child-offset difference e): the byte offset of the representative's T row (-1
+    // where no pair of present children is far apart at that offset: all of them neighbours, or
+    // none present) and the symmetry index, with the target octants of the present pairs in
+    // bits 8..15
+    __shared__ int32_t s_d[27], s_sb[27], s_sm[27];
+    __shared__ int2 s_tx[27][27];
     __shared__ int32_t s_n, s_tmask;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t P = lb / kchunks;
@@ -344,14 +368,16 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
             if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
             pairs |= ((tmask >> ot) & (s_sm[i] >> (ax + 2 * ay + 4 * az)) & 1) << ot;
         }
-        s_tx[i][e] = (pairs && tx >= 0) ? (pairs << 16) | tx : -1;
+        const bool use = pairs && tx >= 0;
+        s_tx[i][e] = make_int2(use ? (tx >> 4) * K * (int)sizeof(C) : -1, (tx & (kNumSym - 1)) | (pairs << 8));
     }
     __syncthreads();
     const int64_t plane = nb * (int64_t)K;
     const int nr = min(RB, nrhs - r0);
-    int kp[kNumSym];
+    int kp8[kNumSym];   // byte offsets of the permuted directions
 #pragma unroll
-    for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[g * K + k];
+    for (int g = 0; g < kNumSym; ++g) kp8[g] = tperm[g * K + k] * (int)sizeof(C);
+    const __amdgpu_buffer_rsrc_t trs = table_rsrc(T, (uint32_t)kNumReps * (uint32_t)K * (uint32_t)sizeof(C));
     C acc[8][RB];
 #pragma unroll
     for (int o = 0; o < 8; ++o)
@@ -372,16 +398,21 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
         }
 #pragma unroll
         for (int e = 0; e < 27; ++e) {
-            const int v = __builtin_amdgcn_readfirstlane(s_tx[i][e]);
-            if (v < 0) continue;
-            const int tx = v & 0xffff, pairs = v >> 16;
-            const C tv = T[(uint64_t)(uint32_t)(tx >> 4) * (uint32_t)K + kp[tx & (kNumSym - 1)]];
+            const int2 v = s_tx[i][e];
+            const int roff = __builtin_amdgcn_readfirstlane(v.x);
+            if (roff < 0) continue;
+            const int gp = __builtin_amdgcn_readfirstlane(v.y);
+            const int pairs = gp >> 8;
+            const C tv = buf_load<C>(trs, kp8[gp & (kNumSym - 1)], roff);
             const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
 #pragma unroll
             for (int ot = 0; ot < 8; ++ot) {
                 const int ax = (ot & 1) + ex, ay = ((ot >> 1) & 1) + ey, az = ((ot >> 2) & 1) + ez;
                 if (ax < 0 || ax > 1 || ay < 0 || ay > 1 || az < 0 || az > 1) continue;
                 if (!((pairs >> ot) & 1)) continue;
+                // an absent pair costs a scalar test; the empty volatile asm keeps the compiler
+                // from turning this branch into multiply-adds and selects
+                __asm__ __volatile__("");
                 const int os = ax + 2 * ay + 4 * az;
 #pragma unroll
                 for (int q = 0; q < RB; ++q) cmac(acc[ot][q], ms[os][q], tv);
