@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
 // by the definition of I(b) (Section 2): the children b of a parent P receive from the children
 // b' of every neighbour P' of P that are not neighbours of b. For P' at offset D from P and
 // octants o(b), o(b'), the transfer vector is 2D + (o(b') - o(b)), one of 27 per D; so a block
-// (P, 256 directions) loads the <= 8 source signatures of each P' once and each of the 27
+// (P, NTH = 128 or 256 directions, whichever leaves fewer idle lanes at this K) loads the <= 8 source signatures of each P' once and each of the 27
 // transfer functions once, and applies them to every child pair they serve (up to 64 pairs),
 // instead of reading one M and one T per pair. T is read through the quadrature symmetry as in
 // m2l_kernel.
@@ -301,8 +301,8 @@ template <> __device__ inline double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r
     return c;
 }
 
-template <class C, int RB>
-__global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
+template <class C, int RB, int NTH>
+__global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
                                                    const int32_t* __restrict__ pslots,
                                                    const int32_t* __restrict__ child_start,
                                                    const int32_t* __restrict__ child_count,
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
     __shared__ int32_t s_n, s_tmask;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t P = lb / kchunks;
-    const int kraw = (lb % kchunks) * 256 + threadIdx.x;
+    const int kraw = (lb % kchunks) * NTH + threadIdx.x;
     const bool kvalid = kraw < K;
     const int k = kvalid ? kraw : K - 1;   // tail lanes compute on a valid direction, store nothing
     const int r0 = blockIdx.y * RB;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void m2lp_kernel(int K, int kchunks,
     }
     __syncthreads();
     const int nn = s_n, tmask = s_tmask;
-    for (int t = threadIdx.x; t < nn * 27; t += 256) {
+    for (int t = threadIdx.x; t < nn * 27; t += NTH) {
         const int i = t / 27, e = t % 27, D = s_d[i];
         const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
         const int code = (2 * (D % 3 - 1) + ex + 3) + 7 * (2 * ((D / 3) % 3 - 1) + ey + 3) +
@@ -857,15 +857,19 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
             const int kch = (Lv.K + 255) / 256;
             if (p->tune.m2l_by_parent) {
                 const int rbp = rb >= 2 ? 2 : 1;
-                const dim3 grid((unsigned)(Pv.n * kch), (nrhs + rbp - 1) / rbp);
+                // 128-direction blocks where they leave fewer idle lanes than 256-direction ones
+                const bool narrow = (Lv.K + 127) / 128 * 128 < (Lv.K + 255) / 256 * 256;
+                const int nth = narrow ? 128 : 256, kc = (Lv.K + nth - 1) / nth;
+                const dim3 grid((unsigned)(Pv.n * kc), (nrhs + rbp - 1) / rbp);
+                auto go = [&](auto kern) {
+                    hipLaunchKernelGGL(kern, grid, dim3(nth), 0, s, Lv.K, kc, Pv.nb_slots, Pv.child_start,
+                                       Pv.child_count, Lv.octant, p->code_map, Lv.tperm, (const C*)Lv.transfer,
+                                       (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                };
                 if (rbp == 2)
-                    hipLaunchKernelGGL((m2lp_kernel<C, 2>), grid, dim3(256), 0, s, Lv.K, kch, Pv.nb_slots,
-                                       Pv.child_start, Pv.child_count, Lv.octant, p->code_map, Lv.tperm,
-                                       (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                    narrow ? go(m2lp_kernel<C, 2, 128>) : go(m2lp_kernel<C, 2, 256>);
                 else
-                    hipLaunchKernelGGL((m2lp_kernel<C, 1>), grid, dim3(256), 0, s, Lv.K, kch, Pv.nb_slots,
-                                       Pv.child_start, Pv.child_count, Lv.octant, p->code_map, Lv.tperm,
-                                       (const C*)Lv.transfer, (const C*)Lv.sigM, (C*)Lv.sigL, Lv.n, nrhs);
+                    narrow ? go(m2lp_kernel<C, 1, 128>) : go(m2lp_kernel<C, 1, 256>);
                 FFMM_LAUNCH_CHECK();
                 continue;
             }
