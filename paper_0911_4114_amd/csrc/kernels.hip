@@ -141,21 +141,22 @@ __global__ void scatter_out(const C* __restrict__ far, const C* __restrict__ nea
 // ------------------------------------------------------------------------------------------
 // P2M (Initialization, Section 2): M_b(s_k) = sum_{i in b} q_i e^{i kappa s_k . (x_i - c_b)}.
 // The quadrature holds every direction with its antipode, so one phase and one sine/cosine per
-// point serve both. Block: one leaf box and 256 antipodal pairs; the box's points in LDS.
+// point serve both. Block: one leaf box and NTH antipodal pairs (64, 128 or 256: the width that
+// leaves the fewest idle lanes at this K); the box's points staged in LDS NTH at a time.
 // ------------------------------------------------------------------------------------------
-template <class R, class C>
-__global__ __launch_bounds__(256) void p2m_kernel(int Kp, int kchunks, const R* __restrict__ dirs,
+template <class R, class C, int NTH>
+__global__ __launch_bounds__(NTH) void p2m_kernel(int Kp, int kchunks, const R* __restrict__ dirs,
                                                   const int32_t* __restrict__ pairs, R kfac,
                                                   const int32_t* __restrict__ start,
                                                   const int32_t* __restrict__ count,
                                                   const R* __restrict__ rel, const C* __restrict__ q,
                                                   C* __restrict__ M, int64_t n, int64_t nb, int K)
 {
-    __shared__ R sx[256], sy[256], sz[256];
-    __shared__ C sq[256];
+    __shared__ R sx[NTH], sy[NTH], sz[NTH];
+    __shared__ C sq[NTH];
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t b = lb / kchunks;
-    const int pi = (lb % kchunks) * 256 + threadIdx.x;
+    const int pi = (lb % kchunks) * NTH + threadIdx.x;
     const bool pvalid = pi < Kp;
     const int64_t r = blockIdx.y;
     int k1 = 0, k2 = 0;
@@ -170,8 +171,8 @@ __global__ __launch_bounds__(256) void p2m_kernel(int Kp, int kchunks, const R* 
     const int s0 = start[b], cnt = count[b];
     // s_k2 = -s_k1: M(s_k1) = A + iB, M(s_k2) = A - iB with A = sum cos(ph) q, B = sum sin(ph) q
     C A = cz<C>(), B = cz<C>();
-    for (int p0 = 0; p0 < cnt; p0 += 256) {
-        const int np = min(256, cnt - p0);
+    for (int p0 = 0; p0 < cnt; p0 += NTH) {
+        const int np = min(NTH, cnt - p0);
         __syncthreads();
         if ((int)threadIdx.x < np) {
             const int64_t i = s0 + p0 + threadIdx.x;
@@ -830,10 +831,21 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         // P2M
         {
             StageScope sc(p, FFMM_PROF_P2M, s);
-            const int kch = (leaf.Kp + 255) / 256;
-            hipLaunchKernelGGL((p2m_kernel<R, C>), dim3((unsigned)(leaf.n * kch), nrhs), dim3(256), 0, s,
-                               leaf.Kp, kch, (const R*)leaf.dirs, leaf.pairs, kfac, p->leaf_start,
-                               p->leaf_count, (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n, leaf.K);
+            int nth = 256;
+            for (int w : {128, 64})
+                if ((leaf.Kp + w - 1) / w * w < (leaf.Kp + nth - 1) / nth * nth) nth = w;
+            const int kch = (leaf.Kp + nth - 1) / nth;
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)(leaf.n * kch), nrhs), dim3(nth), 0, s, leaf.Kp, kch,
+                                   (const R*)leaf.dirs, leaf.pairs, kfac, p->leaf_start, p->leaf_count,
+                                   (const R*)p->rel, qs, (C*)leaf.sigM, n, leaf.n, leaf.K);
+            };
+            if (nth == 64)
+                go(p2m_kernel<R, C, 64>);
+            else if (nth == 128)
+                go(p2m_kernel<R, C, 128>);
+            else
+                go(p2m_kernel<R, C, 256>);
             FFMM_LAUNCH_CHECK();
         }
         // P2P forks after P2M, so that the first far-field kernel is not queued behind it
