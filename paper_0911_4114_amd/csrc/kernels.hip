@@ -472,8 +472,12 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
     const int s0 = start[b], cnt = count[b];
     const C* Lb = L + (r * nb + b) * K;
     for (int t0 = 0; t0 < cnt; t0 += kWave) {
-        const bool valid = t0 + lane < cnt;
-        const int64_t i = s0 + t0 + lane;
+        // g lanes per target split its pairs when the chunk has few targets
+        const int tcnt = min(kWave, cnt - t0);
+        const int g = kWave / tcnt;
+        const int my = lane / g, sub = lane % g;
+        const bool valid = my < tcnt;
+        const int64_t i = s0 + t0 + (valid ? my : 0);
         R x = 0, y = 0, z = 0;
         if (valid) {
             x = -rel[3 * i] * kfac;      // kappa (c_b - x_i), in the phase units of R
@@ -499,12 +503,12 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                 sS[k] = a1 - a2;
             }
             wave_lds_sync();
-            // plain sums over 8 pairs (16 directions), combined with TwoSum
-            for (int kb = 0; kb < nk; kb += 8) {
-                const int ke = min(kb + 8, nk);
+            // each lane: plain sums over 8 of its pairs (16 directions), combined with TwoSum
+            for (int kb = 0; kb < nk; kb += 8 * g) {
+                const int ke = min(kb + 8 * g, nk);
                 R pre[NC], pim[NC];
                 for (int a = 0; a < NC; ++a) pre[a] = pim[a] = 0;
-                for (int k = kb; k < ke; ++k) {
+                for (int k = kb + sub; k < ke; k += g) {
                     R c, sn;
                     cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
                     if (GRAD) {
@@ -529,7 +533,30 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                 }
             }
         }
-        if (valid)   // every point lies in one leaf: a plain store
+        if (g > 1) {
+            // the g lanes of a target combine their compensated sums in lane order, through this
+            // wave's staging arrays (free now; entry a kWave + lane of each, a < NC <= 3)
+            static_assert(3 * kWave <= kL2PChunk, "combine area");
+            wave_lds_sync();
+            for (int a = 0; a < NC; ++a) {
+                sP[a * kWave + lane] = sre[a];
+                sQ[a * kWave + lane] = sim[a];
+                sV[a * kWave + lane] = ere[a];
+                sS[a * kWave + lane] = eim[a];
+            }
+            wave_lds_sync();
+            if (valid && sub == 0)
+                for (int a = 0; a < NC; ++a)
+                    for (int u = 1; u < g; ++u) {
+                        R e1, e2;
+                        two_sum(sre[a], sP[a * kWave + lane + u], sre[a], e1);
+                        two_sum(sim[a], sQ[a * kWave + lane + u], sim[a], e2);
+                        ere[a] += sV[a * kWave + lane + u] + e1;
+                        eim[a] += sS[a * kWave + lane + u] + e2;
+                    }
+            wave_lds_sync();
+        }
+        if (valid && sub == 0)   // every point lies in one leaf: a plain store
             for (int a = 0; a < NC; ++a) out[(r * n + i) * NC + a] = cmk<C>(sre[a] + ere[a], sim[a] + eim[a]);
     }
 }
