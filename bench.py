@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (PMC calibration)")
-    ap.add_argument("--large", action="store_true",
-                    help="also run 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2^23 ellipsoid points, kappa 500, eps 1e-3, 4 RHS run")
     ap.add_argument("--volume", action="store_true",
                     help="also run the volume workload: 2^12..2^22 points uniform in the unit cube, "
                          "kappa = 2 pi N^(1/3) / 2.52, FP32, eps 1e-4, automatic method and depth")
@@ -236,7 +236,7 @@ def main():
         torch.cuda.empty_cache()
 
     large = None
-    if args.large:
+    if not args.no_large:
         nl = 1 << 23
         xl = wl.ellipsoid_points(nl, seed=0)
         ql = wl.complex_normal(nl, seed=1, nrhs=4)
