@@ -46,8 +46,9 @@ typedef enum {
 typedef enum {
     FFMM_FP64 = 0, /* signatures, tables and sums in FP64; complex128 input/output */
     FFMM_FP32 = 1  /* signatures, FFT resampling, M2L, P2M/L2P in FP32 (complex64 I/O); the
-                      transfer-function precompute and the near-field distance and phase stay
-                      in FP64 */
+                      transfer-function precompute and the near-field coordinate differences
+                      and R^2 stay in FP64, and so does the near-field phase when the leaves
+                      span more than 8 revolutions of it (kappa 2 sqrt(3) a_L > 16 pi) */
 } ffmm_precision;
 
 #define FFMM_MAX_LEVELS 22 /* levels 0..21; the Morton keys hold 21 bits per axis */
@@ -77,7 +78,7 @@ typedef struct {
 
 /*
  * FFMM_METHOD_DIRECT evaluates the sum over all pairs (the O(N^2) method the FMM is compared
- * with; FP64 distance and phase as in the near field). FFMM_METHOD_AUTO times, at plan creation,
+ * with; FP64 distance and phase in both precisions). FFMM_METHOD_AUTO times, at plan creation,
  * the direct sum (for n <= 2^18) and the FMM at the automatic depth and its feasible neighbours
  * (one level shallower, one deeper; a level whose leaves cannot reach eps is skipped), with
  * max_rhs unit charges, and keeps the fastest plan: the time-optimal level count and the
