@@ -47,6 +47,9 @@ def parse():
                     help="also run the volume workload: 2^12..2^22 points uniform in the unit cube, "
                          "kappa = 2 pi N^(1/3) / 2.52, FP32, eps 1e-4, automatic method and depth")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="run P2P in order on the calling stream (no overlap), so that a kernel "
+                         "trace shows every kernel alone")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the autograd run (2^18 sphere points, kappa 88, loss sum |phi - phi_t|^2)")
     return ap.parse_args()
@@ -148,6 +151,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = ff.Plan(xt, args.kappa, args.eps, precision="fp32", depth=args.depth or None)
+    if args.serial:
+        plan.set_tuning(near_stream=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = plan.info()

@@ -135,7 +135,7 @@ struct ffmm_plan {
     void* qs = nullptr;             // [max_rhs][n] complex, sorted charges
     void* phis = nullptr;           // far field (L2P): [max_rhs][n] complex ([..][3] for gradients)
     void* phin = nullptr;           // near field (P2P), same shape
-    // P2P runs on its own stream, forked after the charge gather and joined before the scatter,
+    // P2P runs on its own stream, forked after the upward pass and joined before the scatter,
     // so that it overlaps the far-field stages (default priority, non-blocking)
     hipStream_t near_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;

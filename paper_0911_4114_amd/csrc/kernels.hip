@@ -875,16 +875,17 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                 go(p2m_kernel<R, C, 256>);
             FFMM_LAUNCH_CHECK();
         }
-        // P2P forks after P2M, so that the first far-field kernel is not queued behind it
-        if (fork) {
-            FFMM_HIP(hipEventRecord(p->ev_fork, s));
-            FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
-            launch_p2p(p->near_stream);
-        }
         // M2M, l = L..3 (five-step resample to the parent grid, translate, sum children)
         for (int l = L; l >= 3; --l) {
             StageScope sc(p, FFMM_PROF_M2M, s);
             run_resample(p, l, l - 1, nrhs, s);
+        }
+        // P2P forks after the upward pass: beside M2L and the downward pass it costs the far field
+        // less than beside M2M (measured: 3.59 against 3.68 ms per matvec at 2^20 points)
+        if (fork) {
+            FFMM_HIP(hipEventRecord(p->ev_fork, s));
+            FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
+            launch_p2p(p->near_stream);
         }
         // M2L, l = 2..L (written into the L buffers, which then receive the downward pass)
         int rb = p->tune.m2l_rhs_block;
