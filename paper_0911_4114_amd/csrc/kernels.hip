@@ -456,8 +456,11 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
     // per antipodal pair (s, -s) with weighted values u1 = w L(s) = a1 + i b1, u2 = w L(-s):
     // s and P = a1 + a2, Q = b1 - b2, V = b1 + b2, S = a1 - a2, so that the pair contributes
     // (c P - sn Q) + i (c V + sn S) for e^{i ph} = c + i sn, ph = kappa s.(c_b - x_i)
-    __shared__ R sxa[kWpb][kL2PChunk], sya[kWpb][kL2PChunk], sza[kWpb][kL2PChunk];
-    __shared__ R spa[kWpb][kL2PChunk], sqa[kWpb][kL2PChunk], sva[kWpb][kL2PChunk], ssa[kWpb][kL2PChunk];
+    // pairs staged per chunk: 256, or 128 for the FP64 potential (28 KB of LDS per block, so that
+    // several blocks share a CU; the FP64 gradient keeps 256 for its combine area)
+    constexpr int CH = (sizeof(R) == 4 || GRAD) ? kL2PChunk : kL2PChunk / 2;
+    __shared__ R sxa[kWpb][CH], sya[kWpb][CH], sza[kWpb][CH];
+    __shared__ R spa[kWpb][CH], sqa[kWpb][CH], sva[kWpb][CH], ssa[kWpb][CH];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
     if (b >= nb) return;
@@ -486,8 +489,8 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
         }
         R sre[NC], sim[NC], ere[NC], eim[NC];
         for (int a = 0; a < NC; ++a) sre[a] = sim[a] = ere[a] = eim[a] = 0;
-        for (int k0 = 0; k0 < Kp; k0 += kL2PChunk) {
-            const int nk = min(kL2PChunk, Kp - k0);
+        for (int k0 = 0; k0 < Kp; k0 += CH) {
+            const int nk = min(CH, Kp - k0);
             wave_lds_sync();
             for (int k = lane; k < nk; k += kWave) {
                 const int k1 = pairs[2 * (k0 + k)], k2 = pairs[2 * (k0 + k) + 1];
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
         if (g > 1) {
             // the g lanes of a target combine their compensated sums in lane order, through this
             // wave's staging arrays (free now; entry a kWave + lane of each, a < NC <= 3)
-            static_assert(3 * kWave <= kL2PChunk, "combine area");
+            static_assert(NC * kWave <= CH, "combine area");
             wave_lds_sync();
             for (int a = 0; a < NC; ++a) {
                 sP[a * kWave + lane] = sre[a];
