@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -438,42 +439,50 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
 // One wave per leaf box (four per block), one lane per target point; the directions are taken in
 // antipodal pairs (one phase and one sine/cosine per pair), staged in the wave's own LDS in
-// chunks. The sum over k is blocked: plain sums of 16 directions, combined with TwoSum, which
+// chunks. The sum over k is blocked: plain sums of up to 16 directions, combined with TwoSum, which
 // keeps the FP32 accumulation error of the large cancelling terms near the size of the result.
 // ------------------------------------------------------------------------------------------
 constexpr int kL2PChunk = 256;
 
-template <class R, class C, bool GRAD>
+// NR right-hand sides per block (blockIdx.y: the group r0 .. r0 + NR - 1) share each pair's phase and
+// sine/cosine; without GRAD only.
+template <class R, class C, bool GRAD, int NR>
 __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __restrict__ dirs,
                                                     const int32_t* __restrict__ pairs,
                                                     const R* __restrict__ w, R kfac, R kappa,
                                                     const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ count,
                                                     const R* __restrict__ rel, const C* __restrict__ L,
-                                                    C* __restrict__ out, int64_t n, int64_t nb, int K)
+                                                    C* __restrict__ out, int64_t n, int64_t nb, int K, int nrhs)
 {
     constexpr int NC = GRAD ? 3 : 1;
+    static_assert(NR == 1 || !GRAD, "the gradient serves one right-hand side per block");
     // per antipodal pair (s, -s) with weighted values u1 = w L(s) = a1 + i b1, u2 = w L(-s):
     // s and P = a1 + a2, Q = b1 - b2, V = b1 + b2, S = a1 - a2, so that the pair contributes
     // (c P - sn Q) + i (c V + sn S) for e^{i ph} = c + i sn, ph = kappa s.(c_b - x_i)
     // pairs staged per chunk: 256, or 128 for the FP64 potential (28 KB of LDS per block, so that
-    // several blocks share a CU; the FP64 gradient keeps 256 for its combine area)
-    constexpr int CH = (sizeof(R) == 4 || GRAD) ? kL2PChunk : kL2PChunk / 2;
+    // several blocks share a CU; the FP64 gradient keeps 256 for its combine area); with NR
+    // right-hand sides 256 / NR (FP32) or 128 / NR (FP64)
+    constexpr int CH = NR > 1 ? (sizeof(R) == 4 ? kL2PChunk : kL2PChunk / 2) / NR
+                              : ((sizeof(R) == 4 || GRAD) ? kL2PChunk : kL2PChunk / 2);
+    static_assert(CH % 64 == 0, "chunks hold whole runs of 64 pairs");
     __shared__ R sxa[kWpb][CH], sya[kWpb][CH], sza[kWpb][CH];
-    __shared__ R spa[kWpb][CH], sqa[kWpb][CH], sva[kWpb][CH], ssa[kWpb][CH];
+    __shared__ R spa[kWpb][NR][CH], sqa[kWpb][NR][CH], sva[kWpb][NR][CH], ssa[kWpb][NR][CH];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t b = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWpb + wv;
     if (b >= nb) return;
     R* sx = sxa[wv];
     R* sy = sya[wv];
     R* sz = sza[wv];
-    R* sP = spa[wv];
-    R* sQ = sqa[wv];
-    R* sV = sva[wv];
-    R* sS = ssa[wv];
-    const int64_t r = blockIdx.y;
+    R (*sP)[CH] = spa[wv];
+    R (*sQ)[CH] = sqa[wv];
+    R (*sV)[CH] = sva[wv];
+    R (*sS)[CH] = ssa[wv];
+    const int64_t r0 = (int64_t)blockIdx.y * NR;
+    const int nr = min(NR, nrhs - (int)r0);
     const int s0 = start[b], cnt = count[b];
-    const C* Lb = L + (r * nb + b) * K;
+    const int64_t plane = nb * K;
+    const C* Lb = L + r0 * plane + b * K;
     for (int t0 = 0; t0 < cnt; t0 += kWave) {
         // g lanes per target split its pairs when the chunk has few targets
         const int tcnt = min(kWave, cnt - t0);
@@ -487,8 +496,9 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
             y = -rel[3 * i + 1] * kfac;
             z = -rel[3 * i + 2] * kfac;
         }
-        R sre[NC], sim[NC], ere[NC], eim[NC];
-        for (int a = 0; a < NC; ++a) sre[a] = sim[a] = ere[a] = eim[a] = 0;
+        R sre[NR][NC], sim[NR][NC], ere[NR][NC], eim[NR][NC];
+        for (int u = 0; u < NR; ++u)
+            for (int a = 0; a < NC; ++a) sre[u][a] = sim[u][a] = ere[u][a] = eim[u][a] = 0;
         for (int k0 = 0; k0 < Kp; k0 += CH) {
             const int nk = min(CH, Kp - k0);
             wave_lds_sync();
@@ -497,70 +507,97 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                 sx[k] = dirs[3 * k1];
                 sy[k] = dirs[3 * k1 + 1];
                 sz[k] = dirs[3 * k1 + 2];
-                const C l1 = Lb[k1], l2 = Lb[k2];
                 const R w1 = w[k1], w2 = w[k2];
-                const R a1 = w1 * l1.x, b1 = w1 * l1.y, a2 = w2 * l2.x, b2 = w2 * l2.y;
-                sP[k] = a1 + a2;
-                sQ[k] = b1 - b2;
-                sV[k] = b1 + b2;
-                sS[k] = a1 - a2;
+#pragma unroll
+                for (int u = 0; u < NR; ++u) {
+                    R a1 = 0, b1 = 0, a2 = 0, b2 = 0;
+                    if (u < nr) {
+                        const C l1 = Lb[u * plane + k1], l2 = Lb[u * plane + k2];
+                        a1 = w1 * l1.x;
+                        b1 = w1 * l1.y;
+                        a2 = w2 * l2.x;
+                        b2 = w2 * l2.y;
+                    }
+                    sP[u][k] = a1 + a2;
+                    sQ[u][k] = b1 - b2;
+                    sV[u][k] = b1 + b2;
+                    sS[u][k] = a1 - a2;
+                }
             }
             wave_lds_sync();
-            // each lane: plain sums over 8 of its pairs (16 directions), combined with TwoSum
-            for (int kb = 0; kb < nk; kb += 8 * g) {
-                const int ke = min(kb + 8 * g, nk);
-                R pre[NC], pim[NC];
-                for (int a = 0; a < NC; ++a) pre[a] = pim[a] = 0;
+            // each lane: plain sums over up to 8 of its pairs (16 directions), combined with TwoSum;
+            // blocks of 8 g pairs rounded down to a power of two, at most 64, so that they tile every
+            // chunk size alike and a right-hand side gets the same sums alone or in a group
+            const int B = min(64, 1 << (31 - __builtin_clz(8 * g)));
+            for (int kb = 0; kb < nk; kb += B) {
+                const int ke = min(kb + B, nk);
+                R pre[NR][NC], pim[NR][NC];
+                for (int u = 0; u < NR; ++u)
+                    for (int a = 0; a < NC; ++a) pre[u][a] = pim[u][a] = 0;
                 for (int k = kb + sub; k < ke; k += g) {
                     R c, sn;
                     cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
                     if (GRAD) {
                         // (-i kappa s)[c (u1 - u2) + i sn (u1 + u2)] = kappa s (Y - i X)
-                        const R X = c * sS[k] - sn * sV[k], Y = c * sQ[k] + sn * sP[k];
+                        const R X = c * sS[0][k] - sn * sV[0][k], Y = c * sQ[0][k] + sn * sP[0][k];
                         const R sa[3] = {sx[k], sy[k], sz[k]};
-                        for (int a = 0; a < 3; ++a) {
-                            pre[a] += kappa * sa[a] * Y;
-                            pim[a] -= kappa * sa[a] * X;
+                        for (int a = 0; a < NC; ++a) {
+                            pre[0][a] += kappa * sa[a] * Y;
+                            pim[0][a] -= kappa * sa[a] * X;
                         }
                     } else {
-                        pre[0] += c * sP[k] - sn * sQ[k];
-                        pim[0] += c * sV[k] + sn * sS[k];
+#pragma unroll
+                        for (int u = 0; u < NR; ++u) {
+                            pre[u][0] += c * sP[u][k] - sn * sQ[u][k];
+                            pim[u][0] += c * sV[u][k] + sn * sS[u][k];
+                        }
                     }
                 }
-                for (int a = 0; a < NC; ++a) {
-                    R e1, e2;
-                    two_sum(sre[a], pre[a], sre[a], e1);
-                    two_sum(sim[a], pim[a], sim[a], e2);
-                    ere[a] += e1;
-                    eim[a] += e2;
-                }
+                for (int u = 0; u < NR; ++u)
+                    for (int a = 0; a < NC; ++a) {
+                        R e1, e2;
+                        two_sum(sre[u][a], pre[u][a], sre[u][a], e1);
+                        two_sum(sim[u][a], pim[u][a], sim[u][a], e2);
+                        ere[u][a] += e1;
+                        eim[u][a] += e2;
+                    }
             }
         }
         if (g > 1) {
             // the g lanes of a target combine their compensated sums in lane order, through this
-            // wave's staging arrays (free now; entry a kWave + lane of each, a < NC <= 3)
+            // wave's staging arrays, read flat (free now; entry (u NC + a) kWave + lane of each)
             static_assert(NC * kWave <= CH, "combine area");
+            R* cP = &sP[0][0];
+            R* cQ = &sQ[0][0];
+            R* cV = &sV[0][0];
+            R* cS = &sS[0][0];
             wave_lds_sync();
-            for (int a = 0; a < NC; ++a) {
-                sP[a * kWave + lane] = sre[a];
-                sQ[a * kWave + lane] = sim[a];
-                sV[a * kWave + lane] = ere[a];
-                sS[a * kWave + lane] = eim[a];
-            }
+            for (int u = 0; u < NR; ++u)
+                for (int a = 0; a < NC; ++a) {
+                    const int e = (u * NC + a) * kWave + lane;
+                    cP[e] = sre[u][a];
+                    cQ[e] = sim[u][a];
+                    cV[e] = ere[u][a];
+                    cS[e] = eim[u][a];
+                }
             wave_lds_sync();
             if (valid && sub == 0)
-                for (int a = 0; a < NC; ++a)
-                    for (int u = 1; u < g; ++u) {
-                        R e1, e2;
-                        two_sum(sre[a], sP[a * kWave + lane + u], sre[a], e1);
-                        two_sum(sim[a], sQ[a * kWave + lane + u], sim[a], e2);
-                        ere[a] += sV[a * kWave + lane + u] + e1;
-                        eim[a] += sS[a * kWave + lane + u] + e2;
-                    }
+                for (int u = 0; u < NR; ++u)
+                    for (int a = 0; a < NC; ++a)
+                        for (int v = 1; v < g; ++v) {
+                            const int e = (u * NC + a) * kWave + lane + v;
+                            R e1, e2;
+                            two_sum(sre[u][a], cP[e], sre[u][a], e1);
+                            two_sum(sim[u][a], cQ[e], sim[u][a], e2);
+                            ere[u][a] += cV[e] + e1;
+                            eim[u][a] += cS[e] + e2;
+                        }
             wave_lds_sync();
         }
         if (valid && sub == 0)   // every point lies in one leaf: a plain store
-            for (int a = 0; a < NC; ++a) out[(r * n + i) * NC + a] = cmk<C>(sre[a] + ere[a], sim[a] + eim[a]);
+            for (int u = 0; u < nr; ++u)
+                for (int a = 0; a < NC; ++a)
+                    out[((r0 + u) * n + i) * NC + a] = cmk<C>(sre[u][a] + ere[u][a], sim[u][a] + eim[u][a]);
     }
 }
 
@@ -572,16 +609,16 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
 // R and kappa R in FP64; in the FP32 path kappa R is reduced modulo 2 pi in FP64 and the
 // sine/cosine, 1/R and the sums are FP32.
 // ------------------------------------------------------------------------------------------
-// One near-field term of target (xi, yi, zi) and source pj (x, y, z) with charge qj: with GRAD the
-// gradient e^{i kR}(i kR - 1)/R^3 (x_i - x_j) q_j, else e^{i kR}/R q_j, added to acc. R = 0 exactly
-// (the target itself, or a coincident point) contributes nothing. The coordinate differences and
-// R^2 are FP64 always: close pairs lose their digits to cancellation otherwise.
-// FAST (FP32 only, for near-field ranges of at most kFastRev revolutions of the phase): R^2 is
-// rounded to FP32 and 1/R, R and the phase kR/2pi follow in FP32, relative error ~1e-7, so the
-// phase is good to ~1e-6 of a revolution.
+// The charge-independent part of one near-field term: g = e^{i kR}/R, or with GRAD the factor
+// e^{i kR}(i kR - 1)/R^3 and x_i - x_j; pair_apply then adds g q_j (with GRAD (x_i - x_j) g q_j).
+template <class R, class C, bool GRAD> struct NearTerm {
+    C g;
+    R d[GRAD ? 3 : 1];
+};
+
 template <class R, class C, bool GRAD, bool FAST = false>
-__device__ __forceinline__ void pair_term(double xi, double yi, double zi, double4 pj, C qj, double kappa,
-                                          double kappa_rev, C (&acc)[GRAD ? 3 : 1])
+__device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, double zi, double4 pj,
+                                                          double kappa, double kappa_rev)
 {
     const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -619,38 +656,68 @@ __device__ __forceinline__ void pair_term(double xi, double yi, double zi, doubl
         inv = ok ? 1.0 / rr : 0.0;
         if constexpr (GRAD) kr = kappa * rr;
     }
+    NearTerm<R, C, GRAD> t;
     if constexpr (GRAD) {
         const R inv3 = inv * inv * inv;
-        const R gr = (-c - s * kr) * inv3, gi = (c * kr - s) * inv3;
-        const C gq = cmul(cmk<C>(gr, gi), qj);
-        const R d[3] = {(R)dx, (R)dy, (R)dz};
+        t.g = cmk<C>((-c - s * kr) * inv3, (c * kr - s) * inv3);
+        t.d[0] = (R)dx;
+        t.d[1] = (R)dy;
+        t.d[2] = (R)dz;
+    } else {
+        t.g = cmk<C>(c * inv, s * inv);
+    }
+    return t;
+}
+
+template <class R, class C, bool GRAD>
+__device__ __forceinline__ void pair_apply(const NearTerm<R, C, GRAD>& t, C qj, C (&acc)[GRAD ? 3 : 1])
+{
+    if constexpr (GRAD) {
+        const C gq = cmul(t.g, qj);
         for (int a = 0; a < 3; ++a) {
-            acc[a].x += d[a] * gq.x;
-            acc[a].y += d[a] * gq.y;
+            acc[a].x += t.d[a] * gq.x;
+            acc[a].y += t.d[a] * gq.y;
         }
     } else {
-        cmac(acc[0], cmk<C>(c * inv, s * inv), qj);
+        cmac(acc[0], t.g, qj);
     }
 }
 
-template <class R, class C, bool GRAD, bool FAST>
+// One near-field term of target (xi, yi, zi) and source pj (x, y, z) with charge qj: with GRAD the
+// gradient e^{i kR}(i kR - 1)/R^3 (x_i - x_j) q_j, else e^{i kR}/R q_j, added to acc. R = 0 exactly
+// (the target itself, or a coincident point) contributes nothing. The coordinate differences and
+// R^2 are FP64 always: close pairs lose their digits to cancellation otherwise.
+// FAST (FP32 only, for near-field ranges of at most kFastRev revolutions of the phase): R^2 is
+// rounded to FP32 and 1/R, R and the phase kR/2pi follow in FP32, relative error ~1e-7, so the
+// phase is good to ~1e-6 of a revolution.
+template <class R, class C, bool GRAD, bool FAST = false>
+__device__ __forceinline__ void pair_term(double xi, double yi, double zi, double4 pj, C qj, double kappa,
+                                          double kappa_rev, C (&acc)[GRAD ? 3 : 1])
+{
+    pair_apply<R, C, GRAD>(pair_geom<R, C, GRAD, FAST>(xi, yi, zi, pj, kappa, kappa_rev), qj, acc);
+}
+
+// NR right-hand sides per block share each pair's geometry, phase and 1/R (blockIdx.y: the group
+// of right-hand sides r0 .. r0 + NR - 1).
+template <class R, class C, bool GRAD, bool FAST, int NR>
 __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restrict__ xs,
                                                     const C* __restrict__ q,
                                                     const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ count,
                                                     const int32_t* __restrict__ nb_ptr,
                                                     const int32_t* __restrict__ nb_src, double kappa,
-                                                    C* __restrict__ out, int64_t n, int64_t nleaf)
+                                                    C* __restrict__ out, int64_t n, int64_t nleaf, int nrhs)
 {
     constexpr int NC = GRAD ? 3 : 1;
     __shared__ double4 spa[kWpb][kWave];   // staged sources: x, y, z (w unused)
-    __shared__ C sqa[kWpb][kWave];
+    __shared__ C sqa[kWpb][NR][kWave];
     __shared__ C parta[kWpb][NC][kWave];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
     double4* sp = spa[wv];
-    C* sq = sqa[wv];
+    C (*sq)[kWave] = sqa[wv];
     C (*part)[kWave] = parta[wv];
-    const int64_t r = blockIdx.y;
+    const int64_t r0 = (int64_t)blockIdx.y * NR;
+    const int nr = min(NR, nrhs - (int)r0);
     const double kappa_rev = kappa / kTwoPi;
     // A block serves logical blocks of kWpb leaves in a loop (the grid may hold fewer blocks than
     // there are leaves, so that P2P leaves room for the far-field kernels running beside it). With
@@ -688,8 +755,15 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
         const bool valid = my < tcnt;
         const int64_t i = tb + t0 + (valid ? my : 0);
         const double xi = xs[3 * i], yi = xs[3 * i + 1], zi = xs[3 * i + 2];
-        C acc[NC];
-        for (int a = 0; a < NC; ++a) acc[a] = cz<C>();
+        C acc[NR][NC];
+        for (int u = 0; u < NR; ++u)
+            for (int a = 0; a < NC; ++a) acc[u][a] = cz<C>();
+        // the pair's geometry once, then its product with each right-hand side's charge
+        auto term = [&](int t) {
+            const NearTerm<R, C, GRAD> tt = pair_geom<R, C, GRAD, FAST>(xi, yi, zi, sp[t], kappa, kappa_rev);
+#pragma unroll
+            for (int u = 0; u < NR; ++u) pair_apply<R, C, GRAD>(tt, sq[u][t], acc[u]);
+        };
         for (int e = nb_ptr[b]; e < nb_ptr[b + 1]; ++e) {
             const int c = nb_src[e];
             const int sb = start[c], sc = count[c];
@@ -699,34 +773,35 @@ __global__ __launch_bounds__(kWave * kWpb) void p2p_kernel(const double* __restr
                 if (lane < ns) {
                     const int64_t j = sb + s0 + lane;
                     sp[lane] = make_double4(xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], 0.0);
-                    sq[lane] = q[r * n + j];
+#pragma unroll
+                    for (int u = 0; u < NR; ++u) sq[u][lane] = u < nr ? q[(r0 + u) * n + j] : cz<C>();
                 }
                 wave_lds_sync();
                 if (g == 1) {
                     // one target per lane: a loop the whole wave runs in step (lanes past the
                     // chunk repeat its first target and store nothing)
 #pragma unroll 4
-                    for (int t = 0; t < ns; ++t)
-                        pair_term<R, C, GRAD, FAST>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+                    for (int t = 0; t < ns; ++t) term(t);
                 } else if (valid) {
-                    for (int t = sub; t < ns; t += g)
-                        pair_term<R, C, GRAD, FAST>(xi, yi, zi, sp[t], sq[t], kappa, kappa_rev, acc);
+                    for (int t = sub; t < ns; t += g) term(t);
                 }
             }
         }
-        // combine the g partial sums of every target
-        for (int a = 0; a < NC; ++a) part[a][lane] = acc[a];
-        wave_lds_sync();
-        if (valid && sub == 0)
-            for (int a = 0; a < NC; ++a) {
-                C sum = part[a][lane];
-                for (int u = 1; u < g; ++u) {
-                    sum.x += part[a][lane + u].x;
-                    sum.y += part[a][lane + u].y;
+        // combine the g partial sums of every target, one right-hand side at a time
+        for (int u = 0; u < nr; ++u) {
+            for (int a = 0; a < NC; ++a) part[a][lane] = acc[u][a];
+            wave_lds_sync();
+            if (valid && sub == 0)
+                for (int a = 0; a < NC; ++a) {
+                    C sum = part[a][lane];
+                    for (int v = 1; v < g; ++v) {
+                        sum.x += part[a][lane + v].x;
+                        sum.y += part[a][lane + v].y;
+                    }
+                    out[((r0 + u) * n + i) * NC + a] = sum;   // every point lies in one leaf: a plain store
                 }
-                out[(r * n + i) * NC + a] = sum;   // every point lies in one leaf: a plain store
-            }
-        wave_lds_sync();
+            wave_lds_sync();
+        }
     }
     }
 }
@@ -841,14 +916,36 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         // FP32 phase when the near-field range spans few revolutions (sources within two leaf
         // sides per axis: R <= 2 sqrt(3) a)
         const bool fast = sizeof(R) == 4 && p->kappa * 2.0 * std::sqrt(3.0) * p->lev[L].a / kTwoPi <= kFastRev;
+        // right-hand sides sharing each pair's geometry (fewer with gradients and in FP64, whose
+        // per-RHS accumulators take more registers)
+        const int nr_max = gradient ? 2 : (sizeof(R) == 4 ? 8 : 4);
+        const int NRv = nrhs >= 8 && nr_max >= 8 ? 8 : (nrhs >= 4 && nr_max >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
+        const unsigned gy = (unsigned)((nrhs + NRv - 1) / NRv);
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(grid, nrhs), dim3(kWave * kWpb), 0, sn, p->xs, qs, p->leaf_start,
-                               p->leaf_count, p->nb_ptr, p->nb_src, p->kappa, phin, n, (int64_t)nl);
+            hipLaunchKernelGGL(kern, dim3(grid, gy), dim3(kWave * kWpb), 0, sn, p->xs, qs, p->leaf_start,
+                               p->leaf_count, p->nb_ptr, p->nb_src, p->kappa, phin, n, (int64_t)nl, nrhs);
         };
-        if (gradient)
-            fast ? go(p2p_kernel<R, C, true, (sizeof(R) == 4)>) : go(p2p_kernel<R, C, true, false>);
-        else
-            fast ? go(p2p_kernel<R, C, false, (sizeof(R) == 4)>) : go(p2p_kernel<R, C, false, false>);
+        auto pick = [&](auto grad_tag, auto fast_tag) {
+            constexpr bool G = decltype(grad_tag)::value, F = decltype(fast_tag)::value;
+            if constexpr (!G && sizeof(R) == 4) {
+                if (NRv == 8) return go(p2p_kernel<R, C, G, F, 8>);
+            }
+            if constexpr (!G) {
+                if (NRv == 4) return go(p2p_kernel<R, C, G, F, 4>);
+            }
+            if (NRv == 2) return go(p2p_kernel<R, C, G, F, 2>);
+            go(p2p_kernel<R, C, G, F, 1>);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        constexpr bool fp32 = sizeof(R) == 4;
+        if (gradient) {
+            if (fast) pick(T_{}, std::integral_constant<bool, fp32>{});
+            else pick(T_{}, F_{});
+        } else {
+            if (fast) pick(F_{}, std::integral_constant<bool, fp32>{});
+            else pick(F_{}, F_{});
+        }
         FFMM_LAUNCH_CHECK();
     };
     if (fork && !(stages & FFMM_STAGE_FAR)) {
@@ -939,16 +1036,23 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         }
         // L2P
         StageScope sc(p, FFMM_PROF_L2P, s);
+        // right-hand sides sharing each pair's sine/cosine: up to 4 (FP32) or 2 (FP64), one with
+        // gradients
+        const int nr_l2p = gradient ? 1 : (sizeof(R) == 4 && nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
+        auto go_l2p = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nblk(leaf.n, kWpb), (nrhs + nr_l2p - 1) / nr_l2p), dim3(kWave * kWpb),
+                               0, s, leaf.Kp, (const R*)leaf.dirs, leaf.pairs, (const R*)leaf.weights, kfac,
+                               (R)p->kappa, p->leaf_start, p->leaf_count, (const R*)p->rel,
+                               (const C*)leaf.sigL, phis, n, leaf.n, leaf.K, nrhs);
+        };
         if (gradient)
-            hipLaunchKernelGGL((l2p_kernel<R, C, true>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               leaf.Kp, (const R*)leaf.dirs, leaf.pairs, (const R*)leaf.weights, kfac,
-                               (R)p->kappa, p->leaf_start, p->leaf_count, (const R*)p->rel,
-                               (const C*)leaf.sigL, phis, n, leaf.n, leaf.K);
+            go_l2p(l2p_kernel<R, C, true, 1>);
+        else if (nr_l2p == 4) {
+            if constexpr (sizeof(R) == 4) go_l2p(l2p_kernel<R, C, false, 4>);
+        } else if (nr_l2p == 2)
+            go_l2p(l2p_kernel<R, C, false, 2>);
         else
-            hipLaunchKernelGGL((l2p_kernel<R, C, false>), dim3(nblk(leaf.n, kWpb), nrhs), dim3(kWave * kWpb), 0, s,
-                               leaf.Kp, (const R*)leaf.dirs, leaf.pairs, (const R*)leaf.weights, kfac,
-                               (R)p->kappa, p->leaf_start, p->leaf_count, (const R*)p->rel,
-                               (const C*)leaf.sigL, phis, n, leaf.n, leaf.K);
+            go_l2p(l2p_kernel<R, C, false, 1>);
         FFMM_LAUNCH_CHECK();
     }
     if (fork) {
