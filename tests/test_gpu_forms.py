@@ -67,6 +67,28 @@ def test_batched_rhs_equal_single(setup):
         p.matvec(dev_complex(np.ones((5, N)), True))
 
 
+@pytest.mark.parametrize("prec,nrhs", [("fp32", 3), ("fp32", 7), ("fp32", 9), ("fp64", 3), ("fp64", 5)])
+def test_ragged_rhs_groups_equal_single(setup, prec, nrhs):
+    """P2P and L2P take the right-hand sides in groups per block (P2P up to 8, L2P up to 4; fewer
+    in FP64 and with gradients); a last group holding fewer than a full one gives the same bits as
+    single calls, for the potential and the field gradient."""
+    x, xt = setup
+    f32 = prec == "fp32"
+    Q = wl.complex_normal(N, seed=12, nrhs=nrhs)
+    p = ff.Plan(xt, KAPPA, 1e-4 if f32 else 1e-6, precision=prec, max_rhs=nrhs)
+    q = dev_complex(Q, f32)
+    out = p.matvec(q).cpu().numpy()
+    grad = p.field_gradient(q).cpu().numpy()
+    for m in range(nrhs):
+        qm = dev_complex(Q[m], f32)
+        assert np.array_equal(out[m], p.matvec(qm).cpu().numpy()), (prec, nrhs, m)
+        assert np.array_equal(grad[m], p.field_gradient(qm).cpu().numpy()), (prec, nrhs, m)
+    tg = wl.subset(N, 300, seed=3)
+    err = rel_l2(out[nrhs - 1][tg], direct.matvec(x, Q[nrhs - 1], KAPPA, targets=tg))
+    log("ragged %s nrhs %d: last rhs err %.2e" % (prec, nrhs, err))
+    assert err < (1e-4 if f32 else 1e-6)
+
+
 def test_autograd_matches_oracle_gradients(setup):
     x, xt = setup
     n = 3000
