@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="run P2P in order on the calling stream (no overlap), so that a kernel "
                          "trace shows every kernel alone")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch configuration instead of the library's autotuner "
+                         "(implied by --serial; counter and trace runs use it so that every "
+                         "dispatch of a kernel has one configuration)")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the autograd run (2^18 sphere points, kappa 88, loss sum |phi - phi_t|^2)")
     return ap.parse_args()
@@ -151,10 +155,18 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = ff.Plan(xt, args.kappa, args.eps, precision="fp32", depth=args.depth or None)
-    if args.serial:
-        plan.set_tuning(near_stream=0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    tune_s = None
+    if args.serial:
+        plan.set_tuning(near_stream=0)
+    elif not args.no_tune:
+        # the library's autotuner picks the launch configuration on this workload (setup, not
+        # timed, like plan creation)
+        t0 = time.perf_counter()
+        plan.autotune(q32)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
     info = plan.info()
     plan_tuning = plan.tuning()
     log("plan fp32 done in %.2fs depth=%d K=%s ell=%s" % (setup_s, info["depth"], info["K"][2:], info["ell"][2:]))
@@ -164,13 +176,17 @@ def main():
     ms_adj = timed(lambda: plan.adjoint(q32), args.steps, args.warmup)
     log("fp32 adjoint %.3f ms" % ms_adj)
 
-    # per-stage times (separate profiled pass)
+    # per-stage times (separate profiled pass: every stage alone on the calling stream, so P2P
+    # gets the whole GPU instead of the share that the tuned configuration leaves it beside the
+    # far field)
+    plan.set_tuning(p2p_blocks_per_cu=0)
     plan.profile(True)
     prof_steps = max(3, min(args.steps, 10))
     for _ in range(prof_steps):
         plan.matvec(q32)
     prof = plan.profile_read()
     plan.profile(False)
+    plan.set_tuning(**plan_tuning)
     stages = {k: {"ms_per_step": v[0] / prof_steps, "launches_per_step": v[1] / prof_steps}
               for k, v in prof.items()}
     cand = {k: v for k, v in stages.items() if k != "leaf_m2l"}
@@ -385,6 +401,7 @@ def main():
         "adjoint": {"value": n / (ms_adj * 1e-3) / 1e6, "ms_per_step": ms_adj},
         "setup_s": setup_s,
         "tuning": plan_tuning,
+        "autotune_s": tune_s,
         "stages_ms": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
         "fp64": fp64,
         "batched": batched,
