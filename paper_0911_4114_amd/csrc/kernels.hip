@@ -27,21 +27,12 @@ template <class C> __device__ inline C cz() { C c; c.x = 0; c.y = 0; return c; }
 
 template <class C, class R> __device__ inline C cmk(R x, R y) { C c; c.x = x; c.y = y; return c; }
 
-// acc += a * b
 // acc += a b with explicit fused operations, so that the rounding does not depend on how the
 // compiler schedules the surrounding loop (batched and single right-hand sides agree bit for bit)
 template <class C> __device__ inline void cmac(C& acc, C a, C b)
 {
     acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
     acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
-}
-
-template <class C> __device__ inline C cmul(C a, C b)
-{
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
 }
 
 template <class C> __device__ inline C cmulconj(C a, C b)  // a * conj(b)
@@ -548,8 +539,9 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                     } else {
 #pragma unroll
                         for (int u = 0; u < NR; ++u) {
-                            pre[u][0] += c * sP[u][k] - sn * sQ[u][k];
-                            pim[u][0] += c * sV[u][k] + sn * sS[u][k];
+                            // explicit fused multiply-adds: the same rounding in every instantiation
+                            pre[u][0] += fma(c, sP[u][k], -(sn * sQ[u][k]));
+                            pim[u][0] += fma(c, sV[u][k], sn * sS[u][k]);
                         }
                     }
                 }
@@ -658,8 +650,10 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
     }
     NearTerm<R, C, GRAD> t;
     if constexpr (GRAD) {
+        // explicit fused multiply-adds here and in pair_apply: the rounding is the same in every
+        // instantiation, so a right-hand side gets the same bits alone or in a group
         const R inv3 = inv * inv * inv;
-        t.g = cmk<C>((-c - s * kr) * inv3, (c * kr - s) * inv3);
+        t.g = cmk<C>(fma(-s, kr, -c) * inv3, fma(c, kr, -s) * inv3);
         t.d[0] = (R)dx;
         t.d[1] = (R)dy;
         t.d[2] = (R)dz;
@@ -673,10 +667,10 @@ template <class R, class C, bool GRAD>
 __device__ __forceinline__ void pair_apply(const NearTerm<R, C, GRAD>& t, C qj, C (&acc)[GRAD ? 3 : 1])
 {
     if constexpr (GRAD) {
-        const C gq = cmul(t.g, qj);
+        const R gx = fma(t.g.x, qj.x, -(t.g.y * qj.y)), gy = fma(t.g.x, qj.y, t.g.y * qj.x);
         for (int a = 0; a < 3; ++a) {
-            acc[a].x += t.d[a] * gq.x;
-            acc[a].y += t.d[a] * gq.y;
+            acc[a].x = fma(t.d[a], gx, acc[a].x);
+            acc[a].y = fma(t.d[a], gy, acc[a].y);
         }
     } else {
         cmac(acc[0], t.g, qj);
