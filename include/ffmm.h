@@ -216,9 +216,11 @@ ffmm_status ffmm_plan_get_tuning(const ffmm_plan* plan, ffmm_tuning* out);
 /*
  * Autotuner: time matvecs of the nrhs right-hand sides at d_q (device, layout of ffmm_matvec)
  * under candidate launch configurations, by coordinate descent over the fields of ffmm_tuning
- * starting from the plan's current one, and keep the fastest on the plan (also copied to *best
- * when best is not NULL). d_out receives the products (its contents are those of the last
- * candidate). Runs about 25 configurations x 4 matvecs, ordered on hip_stream; synchronises it.
+ * starting from the plan's current one, then a confirmation in which the starting configuration,
+ * the descent's choice and that choice with the other P2P placement are timed in turn over three
+ * rounds; the fastest is kept on the plan (also copied to *best when best is not NULL). d_out
+ * receives the products (its contents are those of the last candidate). Runs about 28
+ * configurations x 6 matvecs, ordered on hip_stream; synchronises it.
  */
 ffmm_status ffmm_plan_autotune(ffmm_plan* plan, const void* d_q, void* d_out, int32_t nrhs,
                                void* hip_stream, ffmm_tuning* best);
