@@ -642,10 +642,16 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
         if constexpr (GRAD) kr = (R)(kappa * rr);
     } else {
+        // 1/R from the hardware reciprocal square root refined by two Newton steps
+        // y <- y (3 - R^2 y^2) / 2 (each squares the relative error), R = R^2 y
         const bool ok = r2 > 0.0;
-        const double rr = sqrt(ok ? r2 : 1.0);
+        const double r2s = ok ? r2 : 1.0;
+        double y = __builtin_amdgcn_rsq(r2s);
+        y = y * fma(-0.5 * r2s, y * y, 1.5);
+        y = y * fma(-0.5 * r2s, y * y, 1.5);
+        const double rr = r2s * y;
         cis(kappa * rr, c, s);
-        inv = ok ? 1.0 / rr : 0.0;
+        inv = ok ? y : 0.0;
         if constexpr (GRAD) kr = kappa * rr;
     }
     NearTerm<R, C, GRAD> t;
