@@ -39,16 +39,19 @@ typedef enum {
     FFMM_ERR_OUT_OF_MEMORY = -2, /* a device or host allocation failed */
     FFMM_ERR_HIP = -3,           /* a HIP runtime call failed (message holds hipGetErrorString) */
     FFMM_ERR_UNSUPPORTED = -4,   /* a valid request this build does not handle */
-    FFMM_ERR_ACCURACY = -5,      /* eps cannot be met at any admissible depth */
+    FFMM_ERR_ACCURACY = -5,      /* eps cannot be met: some level's predicted error (Gegenbauer
+                                    truncation plus the rounding floor of the low-frequency
+                                    breakdown, Sections 2.1 and 3.5.1) exceeds eps at every
+                                    admissible depth; see ffmm_options.best_effort */
     FFMM_ERR_INTERNAL = -6       /* a consistency check inside the library failed */
 } ffmm_status;
 
 typedef enum {
     FFMM_FP64 = 0, /* signatures, tables and sums in FP64; complex128 input/output */
     FFMM_FP32 = 1  /* signatures, FFT resampling, M2L, P2M/L2P in FP32 (complex64 I/O); the
-                      transfer-function precompute and the near-field coordinate differences
-                      and R^2 stay in FP64, and so does the near-field phase when the leaves
-                      span more than 8 revolutions of it (kappa 2 sqrt(3) a_L > 16 pi) */
+                      transfer-function precompute and the near-field distance and phase stay
+                      in FP64 (see ffmm_options.fast_near_phase), the sine/cosine, 1/R and the
+                      near-field sums are FP32 */
 } ffmm_precision;
 
 #define FFMM_MAX_LEVELS 22 /* levels 0..21; the Morton keys hold 21 bits per axis */
@@ -74,7 +77,31 @@ typedef struct {
     int32_t ell_override[FFMM_MAX_LEVELS]; /* > 0 forces ell at that level (tests); 0 = auto */
     int32_t method;          /* ffmm_method: FFMM_METHOD_FMM (default), FFMM_METHOD_DIRECT or
                                 FFMM_METHOD_AUTO */
+    int32_t best_effort;     /* 0 (default): plan creation fails with FFMM_ERR_ACCURACY when a
+                                level's predicted error exceeds eps; 1: build the plan anyway with
+                                the most accurate parameters the precision allows (the predicted
+                                error is reported in ffmm_plan_info.predicted_err) */
+    int32_t fast_near_phase; /* FFMM_FP32 only. 0 (default): the near-field distance R and the
+                                phase kappa R are FP64, the phase reduced modulo one revolution
+                                before the FP32 sine/cosine; 1: where the leaves span at most 8
+                                revolutions of the phase (kappa 2 sqrt(3) a_L <= 16 pi), R^2 is
+                                rounded to FP32 and 1/R, R and the phase follow in FP32 (relative
+                                phase error ~1e-7; faster) */
 } ffmm_options;
+
+/*
+ * Device-memory hooks for the plan (for example a framework's caching allocator). alloc returns
+ * device memory of at least `bytes` bytes usable on `stream` (NULL on failure, which becomes
+ * FFMM_ERR_OUT_OF_MEMORY), free releases a pointer alloc returned. The library calls them only
+ * inside ffmm_plan_create (the plan's tables and workspaces, and temporaries of the set-up) and
+ * ffmm_plan_destroy (which synchronises the device first); ctx is passed through unchanged. The
+ * hooks must stay valid until the plan is destroyed.
+ */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, void* stream);
+} ffmm_allocator;
 
 /*
  * FFMM_METHOD_DIRECT evaluates the sum over all pairs (the O(N^2) method the FMM is compared
@@ -119,12 +146,16 @@ ffmm_status ffmm_options_default(ffmm_options* o);
  *   kappa    : wavenumber, finite and > 0.
  *   eps      : target relative error, 1e-12 <= eps <= 0.5 (1e-7 <= eps for FFMM_FP32).
  *   o        : options or NULL for the defaults.
+ *   alloc    : device-memory hooks (see ffmm_allocator) or NULL for hipMalloc/hipFree; both
+ *              function pointers must be set when alloc is not NULL.
  *   out      : receives the plan.
  * Errors: INVALID_ARG (nulls, ranges, non-finite coordinates), UNSUPPORTED (FP32 with
- * eps < 1e-7), OUT_OF_MEMORY, HIP. Synchronises hip_stream once.
+ * eps < 1e-7; a quadrature of more than 2^27 directions), ACCURACY (eps unreachable, see
+ * FFMM_ERR_ACCURACY and options.best_effort), OUT_OF_MEMORY, HIP. Synchronises hip_stream.
  */
 ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, double eps,
-                             const ffmm_options* o, void* hip_stream, ffmm_plan** out);
+                             const ffmm_options* o, const ffmm_allocator* alloc, void* hip_stream,
+                             ffmm_plan** out);
 
 /*
  * phi = A q (eqn. HelmholtzMatrixVector) for nrhs right-hand sides.
@@ -158,6 +189,23 @@ ffmm_status ffmm_adjoint(ffmm_plan* plan, const void* d_g, void* d_out, int32_t 
  */
 ffmm_status ffmm_field_gradient(ffmm_plan* plan, const void* d_q, void* d_grad, int32_t nrhs,
                                 void* hip_stream);
+
+/*
+ * Gradient of a real loss L(phi), phi = A(x) q, with respect to the point positions, for a fixed
+ * tree (the quantity torch.autograd needs for the points). With G = dL/dRe(phi) + i dL/dIm(phi)
+ * per right-hand side and F the field gradient above,
+ *      gx_i = sum_r Re[ conj(G_{r,i}) F_i(q_r) + q_{r,i} F_i(conj G_r) ]
+ * (A_ij depends on x_i and x_j only through |x_i - x_j|, so both ends of each pair contribute;
+ * the kernel's derivative G'(R) is that of eqn. HelmholtzMatrixVector). Runs the field-gradient
+ * FMM on q_r and conj(G_r) together (in groups of max_rhs / 2 right-hand sides, or one after
+ * the other when max_rhs = 1) and combines the two on the GPU.
+ *   d_q   : device, [nrhs][n] complex charges (caller order).
+ *   d_g   : device, [nrhs][n] complex G (caller order).
+ *   d_gx  : device, [n][3] FP64 output (caller order), overwritten.
+ *   nrhs  : >= 1 (any number; processed in groups).
+ */
+ffmm_status ffmm_position_gradient(ffmm_plan* plan, const void* d_q, const void* d_g, double* d_gx,
+                                   int32_t nrhs, void* hip_stream);
 
 /* Stages timed by the profiling calls below. */
 enum {

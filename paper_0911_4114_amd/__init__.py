@@ -5,14 +5,15 @@ provides device memory and the current stream. The library must be built in-tree
 (``python paper_0911_4114_amd/build.py`` or ``__graft_entry__.build()``); without it every call
 raises.
 """
+import atexit
 import ctypes
-import math
 import os
+import weakref
 
 import numpy as np
 import torch  # imported first so that the library binds to the HIP runtime torch has loaded
 
-__all__ = ["Plan", "FfmmError", "select_level_params", "library_path", "load_library",
+__all__ = ["Plan", "FfmmError", "select_level_params", "library_path", "load_library", "Allocator",
            "FP64", "FP32", "STAGE_NEAR", "STAGE_FAR", "STAGE_ALL", "MAX_LEVELS", "apply"]
 
 FP64, FP32 = 0, 1
@@ -42,7 +43,50 @@ class Options(ctypes.Structure):
                 ("max_leaf_points", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("eps_safety", ctypes.c_double),
                 ("max_rhs", ctypes.c_int32), ("reduce_depth", ctypes.c_int32),
-                ("ell_override", ctypes.c_int32 * MAX_LEVELS), ("method", ctypes.c_int32)]
+                ("ell_override", ctypes.c_int32 * MAX_LEVELS), ("method", ctypes.c_int32),
+                ("best_effort", ctypes.c_int32), ("fast_near_phase", ctypes.c_int32)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """ffmm_allocator: device-memory hooks of a plan."""
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    # ctx carries the device index; NULL on failure (the library reports out of memory)
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(ctx or 0),
+                                                  stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ctx, ptr, stream):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept for the life of the module: the library calls these while plans exist
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+# live plans, closed before the interpreter tears torch down (their memory returns through the
+# hooks above)
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_plans():
+    for pl in list(_LIVE):
+        try:
+            pl.close()
+        except Exception:
+            pass
 
 
 class PlanInfo(ctypes.Structure):
@@ -70,7 +114,8 @@ _P = ctypes.c_void_p
 _SIGS = {
     "ffmm_options_default": [ctypes.POINTER(Options)],
     "ffmm_plan_create": [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                         ctypes.POINTER(Options), _P, ctypes.POINTER(_P)],
+                         ctypes.POINTER(Options), ctypes.POINTER(Allocator), _P, ctypes.POINTER(_P)],
+    "ffmm_position_gradient": [_P, _P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec": [_P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec_stages": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "ffmm_adjoint": [_P, _P, _P, ctypes.c_int32, _P],
@@ -152,11 +197,16 @@ class Plan:
     """A plan for phi = A q with A_ij = e^{i kappa |x_i - x_j|}/|x_i - x_j| (i != j).
 
     points: CUDA float64 tensor [N, 3]. precision 'fp64' (complex128 I/O) or 'fp32' (complex64).
+    allocator: 'torch' (default: the plan's device memory comes from torch's caching allocator
+    through the library's allocator hooks) or None (the library's own hipMalloc).
+    best_effort: build the plan even where eps is out of reach (low-frequency breakdown) instead
+    of raising FfmmError with status -5. fast_near_phase: FP32 near-field phase form (see
+    ffmm_options).
     """
 
     def __init__(self, points, kappa, eps, precision="fp64", depth=None, max_leaf=64,
                  alpha=None, eps_safety=None, max_rhs=1, reduce_depth=True, ell_override=None,
-                 method="fmm"):
+                 method="fmm", best_effort=False, fast_near_phase=False, allocator="torch"):
         lib = load_library()
         if not (isinstance(points, torch.Tensor) and points.is_cuda):
             raise TypeError("points must be a CUDA tensor")
@@ -177,10 +227,20 @@ class Plan:
         o.reduce_depth = 1 if reduce_depth else 0
         for l, v in (ell_override or {}).items():
             o.ell_override[int(l)] = int(v)
+        o.best_effort = 1 if best_effort else 0
+        o.fast_near_phase = 1 if fast_near_phase else 0
+        if allocator == "torch":
+            al = Allocator(ctypes.c_void_p(pts.device.index or 0), _TORCH_ALLOC, _TORCH_FREE)
+            alp = ctypes.byref(al)
+        elif allocator is None:
+            alp = None
+        else:
+            raise ValueError("allocator must be 'torch' or None")
         h = ctypes.c_void_p()
         _check(lib.ffmm_plan_create(ctypes.c_void_p(pts.data_ptr()), pts.shape[0], float(kappa),
-                                    float(eps), ctypes.byref(o), _stream(), ctypes.byref(h)))
+                                    float(eps), ctypes.byref(o), alp, _stream(), ctypes.byref(h)))
         self._h = h
+        _LIVE.add(self)
         self.n = pts.shape[0]
         self.precision = o.precision
         self.cdtype = torch.complex128 if o.precision == FP64 else torch.complex64
@@ -225,6 +285,20 @@ class Plan:
     def field_gradient(self, q):
         """F_i(q) = sum_{j != i} G'(R_ij)(x_i - x_j)/R_ij q_j; shape [..., N, 3]."""
         return self._call(load_library().ffmm_field_gradient, q, width=3)
+
+    def position_gradient(self, q, g):
+        """dL/dx [N, 3] float64 for phi = A(x) q and G = dL/dRe(phi) + i dL/dIm(phi) (q and g of
+        equal shape [N] or [nrhs, N]); computed by the library (ffmm_position_gradient)."""
+        q2, _ = self._prep(q)
+        g2, _ = self._prep(g)
+        if q2.shape != g2.shape:
+            raise ValueError("q and g must have the same shape")
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=q2.device)
+        _check(load_library().ffmm_position_gradient(self._h, ctypes.c_void_p(q2.data_ptr()),
+                                                     ctypes.c_void_p(g2.data_ptr()),
+                                                     ctypes.c_void_p(out.data_ptr()), q2.shape[0],
+                                                     _stream()))
+        return out
 
     # ---- inspection ---------------------------------------------------------------------
     def info(self):
@@ -376,22 +450,14 @@ class _Apply(torch.autograd.Function):
         plan = ctx.plan
         grad = grad.contiguous()
         gq = plan.adjoint(grad) if ctx.needs_input_grad[1] else None
-        gx = None
-        if ctx.needs_input_grad[0]:
-            q2 = q.reshape(-1, plan.n)
-            g2 = grad.reshape(-1, plan.n)
-            both = torch.cat([q2, g2.conj()], dim=0).contiguous()
-            f = plan.field_gradient(both)              # [2 nrhs, N, 3]
-            nr = q2.shape[0]
-            fq, fg = f[:nr], f[nr:]
-            gx = (g2.conj()[..., None] * fq + q2[..., None] * fg).real.sum(dim=0)
-            gx = gx.to(torch.float64)
+        gx = plan.position_gradient(q, grad) if ctx.needs_input_grad[0] else None
         return gx, gq, None
 
 
 def apply(plan, points, q):
-    """Differentiable phi = A q. Backward (C-ABI adjoint and field-gradient calls):
+    """Differentiable phi = A q. Backward (C-ABI adjoint and position-gradient calls):
     dL/dq = conj(A conj(G)) and dL/dx_i = Re[conj(G_i) F_i(q) + q_i F_i(conj G)], with
     G = dL/dRe(phi) + i dL/dIm(phi) (torch's convention). ``points`` must be the tensor the plan
-    was built from; the tree stays fixed."""
+    was built from; the tree stays fixed. Any max_rhs works (the library groups the field
+    gradients of q and conj(G) by what the plan's workspaces hold)."""
     return _Apply.apply(points, q, plan)

@@ -21,6 +21,15 @@ void* DeviceArena::alloc(size_t nbytes)
 {
     void* p = nullptr;
     if (nbytes == 0) nbytes = 16;
+    if (hooks.alloc) {
+        p = hooks.alloc(hooks.ctx, nbytes, (void*)stream);
+        if (!p)
+            fail(FFMM_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL for " +
+                                             std::to_string(nbytes) + " bytes");
+        ptrs.push_back(p);
+        bytes += nbytes;
+        return p;
+    }
     hipError_t e = hipMalloc(&p, nbytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -35,7 +44,12 @@ void* DeviceArena::alloc(size_t nbytes)
 
 void DeviceArena::release()
 {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+        if (hooks.free)
+            hooks.free(hooks.ctx, p, (void*)stream);
+        else
+            (void)hipFree(p);
+    }
     ptrs.clear();
     bytes = 0;
 }
@@ -170,10 +184,12 @@ using namespace ffmm;
 
 // FFMM_METHOD_AUTO: build the candidate plans, time each on unit charges, keep the fastest.
 static ffmm_plan* create_fastest(const double* d_points, int64_t n, double kappa, double eps,
-                                 const ffmm_options& opt, hipStream_t s)
+                                 const ffmm_options& opt, const ffmm_allocator* hooks, hipStream_t s)
 {
     std::vector<ffmm_plan*> plans;
     DeviceArena tmp;
+    if (hooks) tmp.hooks = *hooks;
+    tmp.stream = s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&](ffmm_plan* keep) {
         for (ffmm_plan* q : plans)
@@ -188,20 +204,25 @@ static ffmm_plan* create_fastest(const double* d_points, int64_t n, double kappa
             o.method = method;
             o.depth = depth;
             ffmm_plan* q = nullptr;
-            const ffmm_status st = ffmm_plan_create(d_points, n, kappa, eps, &o, s, &q);
+            const ffmm_status st = ffmm_plan_create(d_points, n, kappa, eps, &o, hooks, s, &q);
             if (st == FFMM_OK) plans.push_back(q);
-            else if (st != FFMM_ERR_OUT_OF_MEMORY) fail(st, g_last_error);
+            // a candidate that does not fit or cannot reach eps is left out
+            else if (st != FFMM_ERR_OUT_OF_MEMORY && st != FFMM_ERR_ACCURACY) fail(st, g_last_error);
             return q;
         };
         ffmm_plan* first = make(FFMM_METHOD_FMM, 0);
-        if (!first) fail(FFMM_ERR_OUT_OF_MEMORY, "no candidate plan fits in device memory");
-        const int d0 = first->depth;
-        const double u = opt.precision == FFMM_FP32 ? kUnitRoundoffFP32 : kUnitRoundoffFP64;
-        for (int d : {d0 - 1, d0 + 1})
-            if (d >= 2 && d <= kMaxDepth && leaf_feasible(kappa * first->side / (double)(1 << d), opt.alpha,
-                                                            eps, u))
-                make(FFMM_METHOD_FMM, d);
+        if (first) {
+            const int d0 = first->depth;
+            const double u = opt.precision == FFMM_FP32 ? kUnitRoundoffFP32 : kUnitRoundoffFP64;
+            for (int d : {d0 - 1, d0 + 1})
+                if (d >= 2 && d <= kMaxDepth &&
+                    leaf_feasible(kappa * first->side / (double)(1 << d), opt.alpha, eps, u))
+                    make(FFMM_METHOD_FMM, d);
+        }
         if (n <= (int64_t(1) << 18)) make(FFMM_METHOD_DIRECT, 0);
+        if (plans.empty())
+            fail(FFMM_ERR_ACCURACY, "no FMM depth reaches eps and the point set is too large for "
+                                    "the direct method (n > 2^18), or no candidate fits in memory");
         // unit charges for every right-hand side
         const size_t cs = opt.precision == FFMM_FP32 ? 8 : 16;
         const size_t cnt = (size_t)opt.max_rhs * n;
@@ -260,6 +281,8 @@ ffmm_status ffmm_options_default(ffmm_options* o)
     o->eps_safety = 0.1;
     o->max_rhs = 1;
     o->reduce_depth = 1;
+    o->best_effort = 0;
+    o->fast_near_phase = 0;
     g_last_error.clear();
     return FFMM_OK;
 }
@@ -285,7 +308,8 @@ ffmm_status ffmm_tuning_default(ffmm_tuning* t)
 }
 
 ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, double eps,
-                             const ffmm_options* o, void* hip_stream, ffmm_plan** out)
+                             const ffmm_options* o, const ffmm_allocator* alloc, void* hip_stream,
+                             ffmm_plan** out)
 {
     ffmm_plan* p = nullptr;
     ffmm_status st = guarded([&] {
@@ -322,15 +346,22 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
             fail(FFMM_ERR_INVALID_ARG, "unknown method");
         if (opt.method == FFMM_METHOD_AUTO && opt.depth != 0)
             fail(FFMM_ERR_INVALID_ARG, "depth must be 0 with FFMM_METHOD_AUTO");
+        if (opt.best_effort != 0 && opt.best_effort != 1) fail(FFMM_ERR_INVALID_ARG, "best_effort must be 0 or 1");
+        if (opt.fast_near_phase != 0 && opt.fast_near_phase != 1)
+            fail(FFMM_ERR_INVALID_ARG, "fast_near_phase must be 0 or 1");
+        if (alloc && (!alloc->alloc || !alloc->free))
+            fail(FFMM_ERR_INVALID_ARG, "allocator needs both its alloc and free hooks");
         int ndev = 0;
         FFMM_HIP(hipGetDeviceCount(&ndev));
         if (ndev < 1) fail(FFMM_ERR_HIP, "no HIP device");
         hipStream_t s = (hipStream_t)hip_stream;
         if (opt.method == FFMM_METHOD_AUTO) {
-            *out = create_fastest(d_points, n, kappa, eps, opt, s);
+            *out = create_fastest(d_points, n, kappa, eps, opt, alloc, s);
             return;
         }
         p = new ffmm_plan();
+        if (alloc) p->arena.hooks = *alloc;
+        p->arena.stream = s;
         p->n = n;
         p->kappa = kappa;
         p->eps = eps;
@@ -403,6 +434,20 @@ ffmm_status ffmm_field_gradient(ffmm_plan* plan, const void* d_q, void* d_grad, 
     return guarded([&] {
         check_call(plan, d_q, d_grad, nrhs);
         run_matvec(plan, d_q, d_grad, nrhs, FFMM_STAGE_ALL, false, true, (hipStream_t)hip_stream);
+        plan->has_run = true;
+    });
+}
+
+ffmm_status ffmm_position_gradient(ffmm_plan* plan, const void* d_q, const void* d_g, double* d_gx,
+                                   int32_t nrhs, void* hip_stream)
+{
+    return guarded([&] {
+        if (!plan) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        if (!d_q || !d_g || !d_gx) fail(FFMM_ERR_INVALID_ARG, "input or output pointer is NULL");
+        if ((const void*)d_gx == d_q || (const void*)d_gx == d_g)
+            fail(FFMM_ERR_INVALID_ARG, "output must not alias an input");
+        if (nrhs < 1) fail(FFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+        run_position_gradient(plan, d_q, d_g, d_gx, nrhs, (hipStream_t)hip_stream);
         plan->has_run = true;
     });
 }

@@ -34,10 +34,19 @@ constexpr int kNumCodes = 343;       // 7^3 offset codes, inner 3^3 unused
 constexpr int kNumReps = 34;         // transfer vectors up to the quadrature's symmetries (Fig. SemiOctant)
 constexpr int kNumSym = 16;          // those symmetries: x <-> y swap, then reflections of x, y, z
 
-// Device allocations owned by a plan.
+// Device allocations owned by a plan. With a caller's allocator (ffmm_allocator) every block
+// comes from its alloc hook and goes back through its free hook; otherwise hipMalloc/hipFree.
 struct DeviceArena {
     std::vector<void*> ptrs;
     size_t bytes = 0;
+    ffmm_allocator hooks{};      // alloc == nullptr: hipMalloc
+    hipStream_t stream = nullptr;
+    // temporaries of the set-up take their memory from the plan's hooks too
+    void inherit(const DeviceArena& o)
+    {
+        hooks = o.hooks;
+        stream = o.stream;
+    }
     void* alloc(size_t nbytes);
     template <class T>
     T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
@@ -164,6 +173,9 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s);
 void build_tables(ffmm_plan* p, hipStream_t s);
 void run_matvec(ffmm_plan* p, const void* q, void* out, int nrhs, int stages, bool conj_io,
                 bool gradient, hipStream_t s);
+// gx = sum_r Re[conj(G_r) F(q_r) + q_r F(conj G_r)] (ffmm_position_gradient)
+void run_position_gradient(ffmm_plan* p, const void* q, const void* g, double* gx, int nrhs,
+                           hipStream_t s);
 
 // Records a HIP event pair around a stage when the plan profiles (no-op otherwise).
 struct StageScope {

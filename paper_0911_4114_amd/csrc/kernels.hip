@@ -130,6 +130,49 @@ __global__ void scatter_out(const C* __restrict__ far, const C* __restrict__ nea
     }
 }
 
+// Position gradient (ffmm_position_gradient): per point, in caller order,
+//   gx_i (+)= sum_{rr < cnt} Re[conj(G_rr,i) F_i(q_rr) + q_rr,i F_i(conj G_rr)]
+// F_i(q_rr) at field-gradient rows fq_row + rr of the far and near results (Morton order, [..][n][3]),
+// F_i(conj G_rr) at rows fg_row + rr; a row base of -1 leaves that term out. Sums in FP64.
+template <class C>
+__global__ void posgrad_combine(const C* __restrict__ far, const C* __restrict__ near,
+                                const int64_t* __restrict__ perm, int64_t n, int cnt, int fq_row,
+                                int fg_row, const C* __restrict__ q, const C* __restrict__ g,
+                                int accumulate, double* __restrict__ gx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (accumulate)
+        for (int a = 0; a < 3; ++a) acc[a] = gx[3 * u + a];
+    auto field = [&](int row, int a) {
+        const int64_t k = ((int64_t)row * n + i) * 3 + a;
+        double fx = 0.0, fy = 0.0;
+        if (far) {
+            fx += (double)far[k].x;
+            fy += (double)far[k].y;
+        }
+        fx += (double)near[k].x;
+        fy += (double)near[k].y;
+        return make_double2(fx, fy);
+    };
+    for (int rr = 0; rr < cnt; ++rr) {
+        const C qv = q[(int64_t)rr * n + u], gv = g[(int64_t)rr * n + u];
+        for (int a = 0; a < 3; ++a) {
+            if (fq_row >= 0) {   // Re[conj(G) F(q)]
+                const double2 f = field(fq_row + rr, a);
+                acc[a] += (double)gv.x * f.x + (double)gv.y * f.y;
+            }
+            if (fg_row >= 0) {   // Re[q F(conj G)]
+                const double2 f = field(fg_row + rr, a);
+                acc[a] += (double)qv.x * f.x - (double)qv.y * f.y;
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) gx[3 * u + a] = acc[a];
+}
+
 // ------------------------------------------------------------------------------------------
 // P2M (Initialization, Section 2): M_b(s_k) = sum_{i in b} q_i e^{i kappa s_k . (x_i - c_b)}.
 // The quadrature holds every direction with its antipode, so one phase and one sine/cosine per
@@ -224,7 +267,7 @@ __global__ __launch_bounds__(256) void m2l_kernel(int K, int kchunks,
     const C* Mk = M + (int64_t)r0 * plane + k;
     int kp[kNumSym];
 #pragma unroll
-    for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[g * K + k];
+    for (int g = 0; g < kNumSym; ++g) kp[g] = tperm[(int64_t)g * K + k];
     // T value of entry e (its packed index is uniform across the block)
     auto tval = [&](int e) {
         const int tx = __builtin_amdgcn_readfirstlane(s_tix[e]);
@@ -306,10 +349,9 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
                                                    C* __restrict__ out, int64_t nb, int nrhs)
 {
     // per occupied neighbour P' of P (compacted): D, first child, octant mask of its children;
-    // per (P', child-offset difference e): the byte offset of the representative's T row (-1
-    // where no pair of present children is far apart at that offset: all of them neighbours, or
-    // none present) and the symmetry index, with the target octants of the present pairs in
-    // bits 8..15
+    // per (P', child-offset difference e): the representative's T row (-1 where no pair of
+    // present children is far apart at that offset: all of them neighbours, or none present)
+    // and the symmetry index, with the target octants of the present pairs in bits 8..15
     __shared__ int32_t s_d[27], s_sb[27], s_sm[27];
     __shared__ int2 s_tx[27][27];
     __shared__ int32_t s_n, s_tmask;
@@ -362,15 +404,17 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
             pairs |= ((tmask >> ot) & (s_sm[i] >> (ax + 2 * ay + 4 * az)) & 1) << ot;
         }
         const bool use = pairs && tx >= 0;
-        s_tx[i][e] = make_int2(use ? (tx >> 4) * K * (int)sizeof(C) : -1, (tx & (kNumSym - 1)) | (pairs << 8));
+        s_tx[i][e] = make_int2(use ? (tx >> 4) : -1, (tx & (kNumSym - 1)) | (pairs << 8));
     }
     __syncthreads();
     const int64_t plane = nb * (int64_t)K;
     const int nr = min(RB, nrhs - r0);
-    int kp8[kNumSym];   // byte offsets of the permuted directions
+    // byte offsets of the permuted directions inside one table row (K sizeof(C) < 2^31: the plan
+    // rejects larger quadratures)
+    int kp8[kNumSym];
 #pragma unroll
-    for (int g = 0; g < kNumSym; ++g) kp8[g] = tperm[g * K + k] * (int)sizeof(C);
-    const __amdgpu_buffer_rsrc_t trs = table_rsrc(T, (uint32_t)kNumReps * (uint32_t)K * (uint32_t)sizeof(C));
+    for (int g = 0; g < kNumSym; ++g) kp8[g] = tperm[(int64_t)g * K + k] * (int)sizeof(C);
+    const uint32_t row_bytes = (uint32_t)K * (uint32_t)sizeof(C);
     C acc[8][RB];
 #pragma unroll
     for (int o = 0; o < 8; ++o)
@@ -392,11 +436,14 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
 #pragma unroll
         for (int e = 0; e < 27; ++e) {
             const int2 v = s_tx[i][e];
-            const int roff = __builtin_amdgcn_readfirstlane(v.x);
-            if (roff < 0) continue;
+            const int rep = __builtin_amdgcn_readfirstlane(v.x);
+            if (rep < 0) continue;
             const int gp = __builtin_amdgcn_readfirstlane(v.y);
             const int pairs = gp >> 8;
-            const C tv = buf_load<C>(trs, kp8[gp & (kNumSym - 1)], roff);
+            // a buffer resource per table row: its 64-bit base is scalar arithmetic, the row
+            // offset never enters a 32-bit byte offset
+            const __amdgpu_buffer_rsrc_t trs = table_rsrc(T + (int64_t)rep * K, row_bytes);
+            const C tv = buf_load<C>(trs, kp8[gp & (kNumSym - 1)], 0);
             const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
 #pragma unroll
             for (int ot = 0; ot < 8; ++ot) {
@@ -866,27 +913,32 @@ __global__ void rel_coords(const double* __restrict__ xs, const int32_t* __restr
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// caller order -> Morton order into the plan's charges at right-hand side r_off.. (+ conjugation)
 template <class R>
-void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages, bool conj_io,
-                  bool gradient, hipStream_t s)
+void gather_t(ffmm_plan* p, const void* qv, int nrhs, bool conj, int r_off, hipStream_t s)
+{
+    using C = typename cplx_t<R>::type;
+    StageScope sc(p, FFMM_PROF_GATHER, s);
+    hipLaunchKernelGGL(gather_q<C>, dim3(nblk(p->n, 256), nrhs), dim3(256), 0, s, (const C*)qv, p->perm,
+                       p->n, conj ? 1 : 0, (C*)p->qs + (int64_t)r_off * p->n);
+    FFMM_LAUNCH_CHECK();
+}
+
+// Everything between the gather and the scatter: from the Morton-ordered charges of nrhs
+// right-hand sides to the far field (p->phis, L2P) and the near field (p->phin, P2P, or the whole
+// sum with the direct method), [nrhs][n] ([nrhs][n][3] with gradient), in Morton order.
+template <class R>
+void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
 {
     using C = typename cplx_t<R>::type;
     const int64_t n = p->n;
     const int L = p->depth;
-    const int width = gradient ? 3 : 1;
     C* qs = (C*)p->qs;
     C* phis = (C*)p->phis;
     C* phin = (C*)p->phin;
     const R kfac = phase_scale<R>(p->kappa);
-
-    {
-        StageScope sc(p, FFMM_PROF_GATHER, s);
-        hipLaunchKernelGGL(gather_q<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)qv,
-                           p->perm, n, conj_io ? 1 : 0, qs);
-        FFMM_LAUNCH_CHECK();
-    }
     if (p->direct) {
-        // all pairs are near: one direct-sum launch, then the scatter
+        // all pairs are near: one direct-sum launch
         if (stages & FFMM_STAGE_NEAR) {
             StageScope sc(p, FFMM_PROF_P2P, s);
             if (gradient)
@@ -897,11 +949,6 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
                                    p->xs, qs, n, p->kappa, phin);
             FFMM_LAUNCH_CHECK();
         }
-        StageScope sc(p, FFMM_PROF_SCATTER, s);
-        hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s, (const C*)nullptr,
-                           (stages & FFMM_STAGE_NEAR) ? (const C*)phin : (const C*)nullptr, p->perm, n,
-                           width, conj_io ? 1 : 0, (C*)outv);
-        FFMM_LAUNCH_CHECK();
         return;
     }
     // P2P needs only the gathered charges: it runs on the plan's near-field stream (not while
@@ -915,7 +962,8 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
         const unsigned grid = (unsigned)(bpc > 0 ? std::min<int64_t>(nlog, (int64_t)p->n_cu * bpc) : nlog);
         // FP32 phase when the near-field range spans few revolutions (sources within two leaf
         // sides per axis: R <= 2 sqrt(3) a)
-        const bool fast = sizeof(R) == 4 && p->kappa * 2.0 * std::sqrt(3.0) * p->lev[L].a / kTwoPi <= kFastRev;
+        const bool fast = sizeof(R) == 4 && p->opt.fast_near_phase &&
+                          p->kappa * 2.0 * std::sqrt(3.0) * p->lev[L].a / kTwoPi <= kFastRev;
         // right-hand sides sharing each pair's geometry (fewer with gradients and in FP64, whose
         // per-RHS accumulators take more registers)
         const int nr_max = gradient ? 2 : (sizeof(R) == 4 ? 8 : 4);
@@ -1062,13 +1110,63 @@ void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages
     } else if (stages & FFMM_STAGE_NEAR) {
         launch_p2p(s);
     }
-    {
-        StageScope sc(p, FFMM_PROF_SCATTER, s);
-        hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s,
-                           (stages & FFMM_STAGE_FAR) ? (const C*)phis : (const C*)nullptr,
-                           (stages & FFMM_STAGE_NEAR) ? (const C*)phin : (const C*)nullptr, p->perm, n,
-                           width, conj_io ? 1 : 0, (C*)outv);
+}
+
+template <class R>
+void run_matvec_t(ffmm_plan* p, const void* qv, void* outv, int nrhs, int stages, bool conj_io,
+                  bool gradient, hipStream_t s)
+{
+    using C = typename cplx_t<R>::type;
+    const int64_t n = p->n;
+    gather_t<R>(p, qv, nrhs, conj_io, 0, s);
+    core_t<R>(p, nrhs, stages, gradient, s);
+    StageScope sc(p, FFMM_PROF_SCATTER, s);
+    const bool far = (stages & FFMM_STAGE_FAR) && !p->direct;
+    hipLaunchKernelGGL(scatter_out<C>, dim3(nblk(n, 256), nrhs), dim3(256), 0, s,
+                       far ? (const C*)p->phis : (const C*)nullptr,
+                       (stages & FFMM_STAGE_NEAR) ? (const C*)p->phin : (const C*)nullptr, p->perm, n,
+                       gradient ? 3 : 1, conj_io ? 1 : 0, (C*)outv);
+    FFMM_LAUNCH_CHECK();
+}
+
+// Position gradient: field gradients of q_r and conj(G_r) through the FMM, combined per point.
+template <class R>
+void run_position_gradient_t(ffmm_plan* p, const void* qv, const void* gv, double* gx, int nrhs,
+                             hipStream_t s)
+{
+    using C = typename cplx_t<R>::type;
+    const int64_t n = p->n;
+    const C* q = (const C*)qv;
+    const C* g = (const C*)gv;
+    const C* far = p->direct ? nullptr : (const C*)p->phis;
+    const C* near = (const C*)p->phin;
+    auto combine = [&](int cnt, int fq_row, int fg_row, int r0, bool accumulate) {
+        hipLaunchKernelGGL(posgrad_combine<C>, dim3(nblk(n, 256)), dim3(256), 0, s, far, near, p->perm, n,
+                           cnt, fq_row, fg_row, q + (int64_t)r0 * n, g + (int64_t)r0 * n,
+                           accumulate ? 1 : 0, gx);
         FFMM_LAUNCH_CHECK();
+    };
+    const int mr = p->opt.max_rhs;
+    if (mr >= 2) {
+        // groups of c right-hand sides: rows 0..c-1 hold q_r, rows c..2c-1 conj(G_r)
+        const int c = mr / 2;
+        for (int r0 = 0; r0 < nrhs; r0 += c) {
+            const int cc = std::min(c, nrhs - r0);
+            gather_t<R>(p, q + (int64_t)r0 * n, cc, false, 0, s);
+            gather_t<R>(p, g + (int64_t)r0 * n, cc, true, cc, s);
+            core_t<R>(p, 2 * cc, FFMM_STAGE_ALL, true, s);
+            combine(cc, 0, cc, r0, r0 > 0);
+        }
+        return;
+    }
+    // one right-hand side of workspace: F(q_r), then F(conj G_r)
+    for (int r = 0; r < nrhs; ++r) {
+        gather_t<R>(p, q + (int64_t)r * n, 1, false, 0, s);
+        core_t<R>(p, 1, FFMM_STAGE_ALL, true, s);
+        combine(1, 0, -1, r, r > 0);
+        gather_t<R>(p, g + (int64_t)r * n, 1, true, 0, s);
+        core_t<R>(p, 1, FFMM_STAGE_ALL, true, s);
+        combine(1, -1, 0, r, true);
     }
 }
 
@@ -1098,6 +1196,14 @@ void run_matvec(ffmm_plan* p, const void* q, void* out, int nrhs, int stages, bo
         run_matvec_t<float>(p, q, out, nrhs, stages, conj_io, gradient, s);
     else
         run_matvec_t<double>(p, q, out, nrhs, stages, conj_io, gradient, s);
+}
+
+void run_position_gradient(ffmm_plan* p, const void* q, const void* g, double* gx, int nrhs, hipStream_t s)
+{
+    if (p->prec == FFMM_FP32)
+        run_position_gradient_t<float>(p, q, g, gx, nrhs, s);
+    else
+        run_position_gradient_t<double>(p, q, g, gx, nrhs, s);
 }
 
 }  // namespace ffmm

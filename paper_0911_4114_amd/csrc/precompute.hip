@@ -294,14 +294,15 @@ __global__ void nphi_error(int rows, int ell, int ncols, int ncand, int emax,
 
 // Alg. Nphi with the band-limited transfer function of r0 = |r0| x (box units) computed on the
 // device by the BMTF kernels (the same quantities the host search forms with O(ell^3) DFTs).
-void select_nphi_device(double ka, double r, double r0, int ell, int ntheta, double eps,
-                        const double* dB, int* nphi, hipStream_t s)
+void select_nphi_device(const DeviceArena& hooks, double ka, double r, double r0, int ell, int ntheta,
+                        double eps, const double* dB, int* nphi, hipStream_t s)
 {
     const int rows = ntheta / 2 + 1, nt = 2 * ell + 1;
     const int ncols = 4 * ((2 * ell + 2 + 3) / 4);
     const int nphi_max = 4 * ((2 * ell + 2 + 64 + 3) / 4);
     const int ncand = nphi_max / 4;
     DeviceArena tmp;
+    tmp.inherit(hooks);
     try {
         std::vector<double> jn(ell + 1), yn(ell + 1);
         sph_bessel_j(ell, ka * r0, jn.data());
@@ -371,6 +372,7 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
     const int nt = 2 * ell + 1;
     const int ncols = 4 * ((2 * ell + 2 + 3) / 4);
     DeviceArena tmp;
+    tmp.inherit(p->arena);
     try {
         const double* dB = bmtf_theta_matrix(tmp, ell, ntheta, s);
         std::vector<int> row_of_k(K);
@@ -550,12 +552,21 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             } else {
                 lp.ell = select_ell(ka, r, r0, eps_l, u, &lp.predicted);
             }
+            // the truncation and rounding floor of this level alone already exceed the target
+            // (low-frequency breakdown at every admissible depth, Section 3.5.1)
+            if (lp.predicted > p->eps && !p->opt.best_effort)
+                fail(FFMM_ERR_ACCURACY,
+                     "level " + std::to_string(l) + " (kappa a = " + std::to_string(ka) +
+                         ") cannot reach eps = " + std::to_string(p->eps) + ": predicted error " +
+                         std::to_string(lp.predicted) +
+                         " (low-frequency breakdown); set options.best_effort to build it anyway");
             lp.ntheta = select_ntheta(ka, r, r0, lp.ell, eps_l);
             lp.nphi.assign(lp.ntheta / 2 + 1, 4);
             DeviceArena bt;
+            bt.inherit(p->arena);
             try {
                 const double* dB = bmtf_theta_matrix(bt, lp.ell, lp.ntheta, s);
-                select_nphi_device(ka, r, r0, lp.ell, lp.ntheta, eps_l, dB, lp.nphi.data(), s);
+                select_nphi_device(p->arena, ka, r, r0, lp.ell, lp.ntheta, eps_l, dB, lp.nphi.data(), s);
             } catch (...) {
                 bt.release();
                 throw;
@@ -564,6 +575,15 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
         }
         p->predicted[l] = L.par.predicted;
         L.nrows = L.par.ntheta / 2 + 1;
+        {
+            // quadrature sizes whose table rows and signatures stay below 2^31 bytes per box
+            // (32-bit byte offsets inside one row in the M2L table reads)
+            int64_t k64 = 0;
+            for (int n = 0; n < L.nrows; ++n) k64 += L.par.nphi[n];
+            if (k64 * (int64_t)(2 * sizeof(R)) > (int64_t)INT32_MAX)
+                fail(FFMM_ERR_UNSUPPORTED, "level " + std::to_string(l) + " quadrature of " +
+                                               std::to_string(k64) + " directions exceeds 2^31 bytes per box");
+        }
         L.row_off.assign(L.nrows + 1, 0);
         for (int n = 0; n < L.nrows; ++n) L.row_off[n + 1] = L.row_off[n] + L.par.nphi[n];
         L.K = L.row_off[L.nrows];

@@ -524,6 +524,7 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s)
 {
     const int64_t n = p->n;
     DeviceArena tmp;
+    tmp.inherit(p->arena);
     try {
         // --- root cube ---------------------------------------------------------------------
         const int nbb = (int)std::min<int64_t>(1024, (n + kBoxBlock - 1) / kBoxBlock);

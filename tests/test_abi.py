@@ -35,6 +35,7 @@ def test_options_default_and_status_strings():
     assert o.precision == 0 and o.max_leaf_points == 64 and o.depth == 0
     assert abs(o.alpha - 0.8) < 1e-15 and abs(o.eps_safety - 0.1) < 1e-15
     assert o.max_rhs == 1 and o.reduce_depth == 1 and o.method == 0
+    assert o.best_effort == 0 and o.fast_near_phase == 0
     assert lib.ffmm_options_default(None) == -1
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.ffmm_status_string(code)
@@ -74,10 +75,10 @@ def test_host_parameter_choice_matches_oracle_wide(ka, eps, prec):
     assert info["alpha"] in (0.8, 1.0)
 
 
-def _create(points_ptr, n, kappa, eps, opts=None):
+def _create(points_ptr, n, kappa, eps, opts=None, alloc=None):
     lib = ff.load_library()
     h = ctypes.c_void_p()
-    st = lib.ffmm_plan_create(points_ptr, n, kappa, eps, opts, None, ctypes.byref(h))
+    st = lib.ffmm_plan_create(points_ptr, n, kappa, eps, opts, alloc, None, ctypes.byref(h))
     return st, lib.ffmm_last_error_message().decode()
 
 
@@ -113,6 +114,18 @@ def test_plan_create_rejects_bad_arguments():
     assert st == -1 and "AUTO" in msg
     o.method = 0
     o.depth = 0
+    o.best_effort = 2
+    st, msg = _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))
+    assert st == -1 and "best_effort" in msg
+    o.best_effort = 0
+    o.fast_near_phase = -1
+    st, msg = _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))
+    assert st == -1 and "fast_near_phase" in msg
+    o.fast_near_phase = 0
+    # an allocator needs both hooks (checked before any device work)
+    half = ff.Allocator(None, ff._TORCH_ALLOC, ctypes.cast(None, ff._FREE_FN))
+    st, msg = _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o), ctypes.byref(half))
+    assert st == -1 and "allocator" in msg
     o.struct_size = 4
     assert _create(dummy, 10, 1.0, 1e-4, ctypes.byref(o))[0] == -1
 
@@ -123,6 +136,7 @@ def test_calls_on_null_plan_fail_cleanly():
     assert lib.ffmm_matvec(None, buf, buf, 1, None) == -1
     assert lib.ffmm_adjoint(None, buf, buf, 1, None) == -1
     assert lib.ffmm_field_gradient(None, buf, buf, 1, None) == -1
+    assert lib.ffmm_position_gradient(None, buf, buf, buf, 1, None) == -1
     assert lib.ffmm_plan_info_get(None, None) == -1
     assert lib.ffmm_profile_enable(None, 1) == -1
     assert lib.ffmm_plan_destroy(None) == 0

@@ -182,3 +182,81 @@ def test_direct_method_and_automatic_choice(setup):
     log("auto method: %s depth %d" % (info["method"], info["depth"]))
     assert info["method"] in ("fmm", "direct")
     assert rel_l2(pa.matvec(dev_complex(q, True)).cpu().numpy(), ref) < 1e-4
+
+
+@pytest.mark.parametrize("prec,max_rhs,nrhs", [("fp64", 1, 1), ("fp64", 4, 3), ("fp32", 1, 2), ("fp32", 2, 3)])
+def test_position_gradient_matches_oracle(setup, prec, max_rhs, nrhs):
+    """ffmm_position_gradient: sum_r Re[conj(G_r) F(q_r) + q_r F(conj G_r)] against the oracle's
+    direct gradients, with one right-hand side of workspace (the two field gradients one after the
+    other) and with groups of max_rhs / 2 (the last group short)."""
+    x, _ = setup
+    n = 3000
+    x = x[:n]
+    xt = dev_points(x)
+    kappa = 30.0
+    f32 = prec == "fp32"
+    Q = wl.complex_normal(n, seed=14, nrhs=nrhs)
+    G = wl.complex_normal(n, seed=15, nrhs=nrhs)
+    if f32:
+        Q = Q.astype(np.complex64).astype(complex)
+        G = G.astype(np.complex64).astype(complex)
+    p = ff.Plan(xt, kappa, 1e-4 if f32 else 1e-6, precision=prec, max_rhs=max_rhs)
+    gx = p.position_gradient(dev_complex(Q, f32), dev_complex(G, f32)).cpu().numpy()
+    assert gx.dtype == np.float64 and gx.shape == (n, 3)
+    ref = np.zeros((n, 3))
+    for r in range(nrhs):
+        Fq = direct.gradient(x, Q[r], kappa)
+        Fg = direct.gradient(x, np.conj(G[r]), kappa)
+        ref += np.real(np.conj(G[r])[:, None] * Fq + Q[r][:, None] * Fg)
+    err = rel_l2(gx, ref)
+    log("position gradient %s max_rhs %d nrhs %d: err %.3e" % (prec, max_rhs, nrhs, err))
+    assert err < (1e-3 if f32 else 1e-5)
+
+
+def test_accuracy_unreachable_and_best_effort(setup):
+    """A leaf level in the low-frequency breakdown (ka = 1, FP32, eps 1e-4: predicted 2e-3) makes
+    plan creation fail with FFMM_ERR_ACCURACY; best_effort builds it and reports the prediction."""
+    x = wl.cube_points(2000, seed=0)
+    xt = dev_points(x)
+    side = float((x.max(axis=0) - x.min(axis=0)).max())
+    kappa = 1.0 / (side / 4)
+    with pytest.raises(ff.FfmmError) as ei:
+        ff.Plan(xt, kappa, 1e-4, precision="fp32", depth=2)
+    assert ei.value.status == -5 and "breakdown" in ei.value.message
+    p = ff.Plan(xt, kappa, 1e-4, precision="fp32", depth=2, best_effort=True)
+    pred = max(p.info()["predicted_err"][2:])
+    assert pred > 1e-4
+    q = wl.complex_normal(len(x), seed=1)
+    out = p.matvec(dev_complex(q, True)).cpu().numpy()
+    err = rel_l2(out, direct.matvec(x, q, kappa))
+    log("best effort: predicted %.2e measured %.2e" % (pred, err))
+    assert err < 10 * pred
+    # the automatic depth lowers the depth until the leaves reach eps: FP64 at the same points
+    # with a 1e-6 target still builds (at depth 2), and eps below what any depth reaches fails
+    with pytest.raises(ff.FfmmError) as ei:
+        ff.Plan(xt, kappa, 1e-8, precision="fp64")
+    assert ei.value.status == -5
+
+
+def test_torch_allocator_supplies_plan_memory(setup):
+    """With allocator='torch' the plan's tables and workspaces come from torch's caching
+    allocator through the ffmm_allocator hooks (and go back to it when the plan is closed); with
+    allocator=None the library allocates them itself. Both give the same products."""
+    x, xt = setup
+    q = dev_complex(wl.complex_normal(len(x), seed=16), True)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    p = ff.Plan(xt, KAPPA, 1e-4, precision="fp32", allocator="torch")
+    held = torch.cuda.memory_allocated() - before
+    dev_bytes = p.info()["device_bytes"]
+    log("torch allocator: plan holds %d bytes, torch counts %d" % (dev_bytes, held))
+    assert dev_bytes > 0 and held >= dev_bytes
+    out_t = p.matvec(q).cpu().numpy()
+    p.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < dev_bytes
+    before = torch.cuda.memory_allocated()
+    ph = ff.Plan(xt, KAPPA, 1e-4, precision="fp32", allocator=None)
+    assert torch.cuda.memory_allocated() - before < ph.info()["device_bytes"]
+    assert np.array_equal(ph.matvec(q).cpu().numpy(), out_t)
+    ph.close()
