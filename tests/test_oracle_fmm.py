@@ -290,3 +290,83 @@ def test_fmm_multilevel_matches_single_level():
     for depth in (2, 3, 4):
         out = Plan(x, k, 1e-5, depth=depth).matvec(q)
         assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-5, depth
+
+
+# --- multilevel accuracy with two points (Section 3.5.2) ----------------------------------------
+
+def _two_point_plan(kappa, xj, xi, depth, **kw):
+    """Plan over a source point x_j (charge 1) and a target x_i (charge 0) in level-2 boxes of side
+    1 whose centres differ by r0 = (2, 0, 0) (one buffer box), with two uncharged points fixing
+    the root cube to [0, 4]^3. The pair meets only through the level-2 transfer pass; the
+    transfer functions of every other offset (which only carry zero charges here) are left zero,
+    so only T_{(-2,0,0)} at level 2 is built. Returns the plan and phi_i."""
+    from oracle.transfer import transfer_table
+    frame = np.array([[0.0, 0.0, 0.5], [4.0, 4.0, 4.0]])
+    x = np.vstack([xj, xi, frame])
+    p = Plan(x, kappa, kw.pop("eps", None), depth=depth, **kw)
+    for l in range(2, depth + 1):
+        p._tables[l] = np.zeros((343, p.quads[l].K), dtype=np.complex128)
+    code = (-2 + 3) + 7 * 3 + 49 * 3        # source minus target = (-2, 0, 0) box sides
+    p._tables[2][code] = transfer_table(kappa, np.array([-2.0, 0.0, 0.0]), p.quads[2])
+    return p, p.matvec(np.array([1.0, 0.0, 0.0, 0.0], dtype=np.complex128))[1]
+
+
+def _gegenbauer_value(kappa, r, r0, ell):
+    """The truncated addition theorem (Section 2.1, eqn. eps_G's series) for r and r0."""
+    from oracle import special as osp
+    n = np.arange(ell + 1)
+    cg = float(r @ r0) / (np.linalg.norm(r) * np.linalg.norm(r0))
+    P = osp.legendre_table(ell, np.array([cg]))[:, 0]
+    jn = osp.sph_jn(ell, kappa * np.linalg.norm(r))
+    hn = osp.sph_h1(ell, kappa * np.linalg.norm(r0))
+    return complex(np.sum(1j * kappa * ((-1.0) ** n) * (2 * n + 1) * hn * jn * P))
+
+
+def test_multilevel_interpolation_error_independent_of_depth():
+    """Fig. Error_Quad (Section 3.5.2): two points at opposite corners of their level-2 boxes
+    (|r| = sqrt(3)), kappa = 100, alpha = 0.8, a_2 = 1, transfer at level 2 and L = 2..8 levels in
+    all. eps_G^L is one series for every L; eps_I^L = phi^L - series differs from eps_I^2 (one
+    level, no interpolation) by far less than the target: the up- and downward passes add almost
+    nothing. A wrong translation, resample or level chain makes the L > 2 results drift."""
+    kappa, dd = 100.0, 1e-9
+    xj = np.array([dd, dd, dd])
+    xi = np.array([3.0 - dd, 1.0 - dd, 1.0 - dd])
+    rr = (xi - np.array([2.5, 0.5, 0.5])) - (xj - np.array([0.5, 0.5, 0.5]))
+    exact = np.exp(1j * kappa * np.linalg.norm(xi - xj)) / np.linalg.norm(xi - xj)
+    for eps in (1e-3, 1e-6):
+        ei = {}
+        for L in (2, 3, 5, 8):
+            p, phi = _two_point_plan(kappa, xj, xi, L, eps=eps, alpha=0.8, eps_safety=1.0)
+            series = _gegenbauer_value(kappa, rr, np.array([2.0, 0.0, 0.0]), p.quads[2].ell)
+            ei[L] = phi - series
+            assert abs(abs(phi - exact) - abs(ei[2] + series - exact)) < 0.01 * eps
+        drift = max(abs(ei[L] - ei[2]) for L in (3, 5, 8))
+        assert drift < 0.01 * eps, (eps, drift)
+
+
+def test_quadrature_converges_to_gegenbauer_error():
+    """Fig. GegError_Quad (Section 3.5.2): kappa = 100, alpha = 1/sqrt(3), a_2 = 1, two active
+    levels (the transfer at level 2, interpolation and anterpolation to level 3). With ell held
+    where the Gegenbauer error of the design radius |r| = 1 is 1e-6 or 1e-10, and the quadrature
+    grown by lowering its own target, the total error becomes the truncation error: eps_T ->
+    eps_G. The level-2 quadrature sizes fall in the figure's range (14 000 .. 28 000)."""
+    from oracle.quadrature import level_quadrature, gegenbauer_error
+    kappa = 100.0
+    h = 0.5 / np.sqrt(3.0)
+    xj = np.full(3, 0.5 - h)
+    xi = np.array([2.5 + h, 0.5 + h, 0.5 + h])
+    rr = (xi - np.array([2.5, 0.5, 0.5])) - (xj - np.array([0.5, 0.5, 0.5]))   # |r| = 1
+    exact = np.exp(1j * kappa * np.linalg.norm(xi - xj)) / np.linalg.norm(xi - xj)
+    geg = gegenbauer_error(kappa * 1.0, 1.0, 2.0, 200)
+    alpha = 1.0 / np.sqrt(3.0)
+    for target in (1e-6, 1e-10):
+        ell = int(np.nonzero(geg[1:] < target)[0][0]) + 1
+        eg = abs(_gegenbauer_value(kappa, rr, np.array([2.0, 0.0, 0.0]), ell) - exact)
+        gap = []
+        for eps_q in (1e-2, 1e-6, 1e-12):
+            q2, _ = level_quadrature(kappa, alpha, eps_q, ell=ell)
+            q3, _ = level_quadrature(kappa / 2.0, alpha, eps_q)
+            assert 14000 <= q2.K <= 28000
+            _, phi = _two_point_plan(kappa, xj, xi, 3, alpha=alpha, quads={2: q2, 3: q3})
+            gap.append(abs(abs(phi - exact) - eg) / eg)
+        assert gap[-1] < 0.05 and gap[0] > 10.0 * gap[-1], (target, gap)

@@ -271,3 +271,50 @@ def test_quadrature_closed_under_antipode(ka, eps):
     # the pole rows hold N_phi copies of one direction; elsewhere the antipode is unique
     interior = np.abs(d[:, 2]) < 1 - 1e-12
     assert len(np.unique(j[interior])) == interior.sum()
+
+
+def test_rounding_floor_tracks_breakdown_error():
+    """Low-frequency breakdown (Sections 2.1, 3.5.1). With ell six past the breakdown optimum
+    for ka = 0.5 .. 3 (FP64), the single-level error (worst-case r, r0 along z and x, and random
+    r) is rounding, not truncation: it follows the rounding floor over five decades (1e5 at
+    ka = 0.5 down to 1e-2 at ka = 3) at 1 .. 8 times the floor, whose coherent part carries the
+    factor FLOOR_SCALE = 1/4. A floor with h_n at the wrong argument, without the (2n + 1), or
+    with another power of ka misses this band by orders of magnitude."""
+    u = quadrature.UNIT_ROUNDOFF["fp64"]
+    alpha = 1.0 / np.sqrt(3.0)
+    for ka in (0.5, 1.0, 2.0, 3.0):
+        ell0, _ = quadrature.select_ell(ka, 1.0, 2.0, 0.0, u)
+        ell = ell0 + 6
+        floor = quadrature.rounding_floor(ka, 2.0, ell, u)[ell]
+        q, _ = quadrature.level_quadrature(ka, alpha, 1e-14, ell=ell)
+        s, w = q.dirs(), q.weights()
+        worst = 0.0
+        for r0dir, rdir in [((0, 0, 1), (0, 0, 1)), ((0, 0, 1), (0, 0, -1)),
+                            ((1, 0, 0), (1, 0, 0)), ((1, 0, 0), (-1, 0, 0)), ((1, 2, 2), None)]:
+            r0 = 2.0 * np.asarray(r0dir, float) / np.linalg.norm(r0dir)
+            tab = transfer.transfer_table(ka, r0, q)
+            d = (np.random.default_rng(0).standard_normal((24, 3)) if rdir is None
+                 else np.asarray([rdir], float))
+            rr = d / np.linalg.norm(d, axis=1, keepdims=True)          # |r| = alpha sqrt(3) = 1
+            quadv = (np.exp(1j * ka * (rr @ s.T)) * (w * tab)).sum(axis=1)
+            big = np.linalg.norm(rr + r0, axis=1)
+            worst = max(worst, np.abs(quadv - np.exp(1j * ka * big) / big).max())
+        assert floor <= worst <= 8.0 * floor, (ka, ell, floor, worst)
+
+
+def test_predicted_error_bounds_breakdown_matvec():
+    """The predicted error the oracle reports where eps is out of reach (ell at the breakdown
+    optimum, Section 3.5.1) against the whole matvec's relative L2 error: 1500 points in the unit
+    cube, depth 2, leaf ka = 0.5 .. 3, FP64, eps 1e-9 (unreachable). The measured error lies at
+    0.1 .. 2 times the prediction (0.25 .. 1 when this was written)."""
+    from oracle.ffmm import Plan
+    from oracle import direct
+    rng = np.random.default_rng(0)
+    x = rng.random((1500, 3))
+    q = rng.standard_normal(1500) + 1j * rng.standard_normal(1500)
+    for ka in (0.5, 1.0, 2.0, 3.0):
+        kappa = 4.0 * ka
+        p = Plan(x, kappa, 1e-9, depth=2, alpha=1.0 / np.sqrt(3.0), eps_safety=1.0)
+        ref = direct.matvec(x, q, kappa)
+        err = np.linalg.norm(p.matvec(q) - ref) / np.linalg.norm(ref)
+        assert 0.1 * p.predicted[2] <= err <= 2.0 * p.predicted[2], (ka, err, p.predicted[2])
