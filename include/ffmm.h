@@ -207,6 +207,27 @@ ffmm_status ffmm_field_gradient(ffmm_plan* plan, const void* d_q, void* d_grad, 
 ffmm_status ffmm_position_gradient(ffmm_plan* plan, const void* d_q, const void* d_g, double* d_gx,
                                    int32_t nrhs, void* hip_stream);
 
+/*
+ * Allocation-free variant of ffmm_matvec, for callers that cannot allocate device memory during
+ * the call (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same product, arguments, layout and limits as ffmm_matvec, and the same kernels; the per-call
+ * workspaces (the charges in Morton order, the far- and near-field partial results and the
+ * resample intermediates, about 3 N nrhs complex values plus the two resample buffers of the
+ * plan scaled to nrhs) come from one static device array of FFMM_STATIC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends, instead of the plan's own
+ * buffers. The call allocates nothing (no hipMalloc, hipFree or event creation; stage profiling
+ * is off for it). Every region of the array that a call reads is written earlier in that call,
+ * so nothing carries over from the previous call.
+ *   Errors: as ffmm_matvec; UNSUPPORTED when the workspace of nrhs right-hand sides exceeds
+ *   FFMM_STATIC_SCRATCH_BYTES (the message states both sizes); INVALID_ARG when the current
+ *   device is not the plan's.
+ *   Calls that overlap in time on one GPU (other streams, other threads, other plans) share the
+ *   array and race: the caller orders them, e.g. on one stream.
+ */
+#define FFMM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+ffmm_status ffmm_matvec_static(ffmm_plan* plan, const void* d_q, void* d_phi, int32_t nrhs,
+                               void* hip_stream);
+
 /* Stages timed by the profiling calls below. */
 enum {
     FFMM_PROF_GATHER = 0, /* caller order -> Morton order (+ conjugation) */

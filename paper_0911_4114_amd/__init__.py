@@ -117,6 +117,7 @@ _SIGS = {
                          ctypes.POINTER(Options), ctypes.POINTER(Allocator), _P, ctypes.POINTER(_P)],
     "ffmm_position_gradient": [_P, _P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec": [_P, _P, _P, ctypes.c_int32, _P],
+    "ffmm_matvec_static": [_P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec_stages": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "ffmm_adjoint": [_P, _P, _P, ctypes.c_int32, _P],
     "ffmm_field_gradient": [_P, _P, _P, ctypes.c_int32, _P],
@@ -259,11 +260,18 @@ class Plan:
             raise ValueError("input must have shape [N] or [nrhs, N]")
         return q2.contiguous(), squeeze
 
-    def _call(self, fn, q, width=1, stages=None):
+    def _call(self, fn, q, width=1, stages=None, out=None):
         q2, squeeze = self._prep(q)
         nrhs = q2.shape[0]
         shape = (nrhs, self.n) if width == 1 else (nrhs, self.n, width)
-        out = torch.empty(shape, dtype=self.cdtype, device=q2.device)
+        if out is None:
+            out = torch.empty(shape, dtype=self.cdtype, device=q2.device)
+        elif (out.dtype != self.cdtype or out.device != q2.device or not out.is_contiguous()
+              or out.numel() != nrhs * self.n * width):
+            raise ValueError("out must be a contiguous %s tensor of %d elements on %s"
+                             % (self.cdtype, nrhs * self.n * width, q2.device))
+        else:
+            out = out.view(shape)
         args = [self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out.data_ptr()), nrhs]
         if stages is not None:
             args.append(int(stages))
@@ -273,6 +281,12 @@ class Plan:
     def matvec(self, q):
         """phi = A q; q [N] or [nrhs, N] in the caller's order."""
         return self._call(load_library().ffmm_matvec, q)
+
+    def matvec_static(self, q, out=None):
+        """phi = A q through ffmm_matvec_static: the library allocates nothing during the call (its
+        per-call workspaces live in one fixed device array of the library); pass ``out`` (a
+        contiguous tensor of the result's size) to avoid the output allocation here as well."""
+        return self._call(load_library().ffmm_matvec_static, q, out=out)
 
     def matvec_stages(self, q, stages):
         """Only the selected parts: STAGE_NEAR (P2P), STAGE_FAR (the FMM far field) or both."""

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_ffmm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "params.cpp", "tree.hip", "precompute.hip", "kernels.hip", "resample.hip"]
+SOURCES = ["api.cpp", "params.cpp", "tree.hip", "precompute.hip", "kernels.hip", "resample.hip", "static_ws.hip"]
 ARCH = os.environ.get("FFMM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -114,6 +114,18 @@ static ffmm_status guarded(F&& f)
     }
 }
 
+ffmm_status guarded_call(const std::function<void()>& f) { return guarded(f); }
+
+void check_call(ffmm_plan* plan, const void* in, void* out, int32_t nrhs)
+{
+    if (!plan) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+    if (!in || !out) fail(FFMM_ERR_INVALID_ARG, "input or output pointer is NULL");
+    if (in == out) fail(FFMM_ERR_INVALID_ARG, "input and output must not alias");
+    if (nrhs < 1 || nrhs > plan->opt.max_rhs)
+        fail(FFMM_ERR_INVALID_ARG, "nrhs must lie in [1, max_rhs] (max_rhs = " +
+                                       std::to_string(plan->opt.max_rhs) + ")");
+}
+
 static size_t csize(const ffmm_plan* p) { return p->prec == FFMM_FP32 ? 8 : 16; }
 
 static void allocate_workspaces(ffmm_plan* p)
@@ -371,6 +383,7 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
         {
             int dev = 0;
             FFMM_HIP(hipGetDevice(&dev));
+            p->device = dev;
             FFMM_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         }
         if (opt.method == FFMM_METHOD_DIRECT) {
@@ -393,15 +406,6 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
     return st;
 }
 
-static void check_call(ffmm_plan* plan, const void* in, void* out, int32_t nrhs)
-{
-    if (!plan) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
-    if (!in || !out) fail(FFMM_ERR_INVALID_ARG, "input or output pointer is NULL");
-    if (in == out) fail(FFMM_ERR_INVALID_ARG, "input and output must not alias");
-    if (nrhs < 1 || nrhs > plan->opt.max_rhs)
-        fail(FFMM_ERR_INVALID_ARG, "nrhs must lie in [1, max_rhs] (max_rhs = " +
-                                       std::to_string(plan->opt.max_rhs) + ")");
-}
 
 ffmm_status ffmm_matvec_stages(ffmm_plan* plan, const void* d_q, void* d_phi, int32_t nrhs,
                                int32_t stages, void* hip_stream)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,7 @@ struct ffmm_plan {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ffmm_tuning tune{};             // launch configuration (ffmm_plan_set_tuning)
     int32_t* code_map = nullptr;    // [343] offset code -> 16 rep + g, -1 for the inner codes
+    int device = 0;                 // HIP device the plan was created on
     int n_cu = 0;                   // compute units of the plan's device
     void* scratch1 = nullptr;       // resample workspaces
     void* scratch2 = nullptr;
@@ -168,6 +170,12 @@ struct ffmm_plan {
 };
 
 namespace ffmm {
+
+// Runs f, turning a library Error (or any exception) into a status and the thread's last error
+// message; nothing throws across the C ABI.
+ffmm_status guarded_call(const std::function<void()>& f);
+// Argument checks shared by the matvec-type entry points (plan, pointers, nrhs <= max_rhs).
+void check_call(ffmm_plan* plan, const void* in, void* out, int32_t nrhs);
 
 void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s);
 void build_tables(ffmm_plan* p, hipStream_t s);
