@@ -268,10 +268,17 @@ typedef struct {
                                    largest that does not exceed nrhs */
     int32_t rs_slab[4];         /* FP32 resample k-slab depth (16, 32 or 64) of step 1, steps 2+3,
                                    upward steps 4+5 and downward steps 4+5; default 16, 32, 32, 16 */
-    int32_t m2l_by_parent;      /* 1 (default): M2L by parent pairs, each source signature and
-                                   transfer function read once per parent pair (2.5x faster at the
-                                   leaves of a volume distribution, equal on surfaces); 0: one
-                                   target box per block over its interaction list */
+    int32_t m2l_by_parent;      /* M2L form. 2 (default): by parent pairs, with the transfer
+                                   functions of a chunk of m2l_chunk directions gathered into LDS
+                                   once per block and reused for a range of parents (FP32 plans;
+                                   FP64 plans take form 1); 1: by parent pairs, each source
+                                   signature and transfer function read once per parent pair (2.5x
+                                   faster than 0 at the leaves of a volume distribution); 0: one
+                                   target box per block over its interaction list. Forms 1 and 2
+                                   give the same bits. */
+    int32_t m2l_chunk;          /* directions per block of M2L form 2: 64 (158 KB of LDS, one block
+                                   per compute unit), 48 (default; 121 KB, leaving room for a P2P
+                                   block beside it) or 32 (81 KB) */
 } ffmm_tuning;
 
 /* Fill *t with the defaults listed above. t must not be NULL. */

@@ -105,10 +105,12 @@ class PlanInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("near_stream", ctypes.c_int32),
                 ("p2p_blocks_per_cu", ctypes.c_int32), ("m2l_rhs_block", ctypes.c_int32),
-                ("rs_slab", ctypes.c_int32 * 4), ("m2l_by_parent", ctypes.c_int32)]
+                ("rs_slab", ctypes.c_int32 * 4), ("m2l_by_parent", ctypes.c_int32),
+                ("m2l_chunk", ctypes.c_int32)]
 
 
-TUNING_FIELDS = ("near_stream", "p2p_blocks_per_cu", "m2l_rhs_block", "rs_slab", "m2l_by_parent")
+TUNING_FIELDS = ("near_stream", "p2p_blocks_per_cu", "m2l_rhs_block", "rs_slab", "m2l_by_parent",
+                 "m2l_chunk")
 
 _P = ctypes.c_void_p
 _SIGS = {
@@ -394,7 +396,7 @@ class Plan:
     def _tuning_dict(t):
         return {"near_stream": t.near_stream, "p2p_blocks_per_cu": t.p2p_blocks_per_cu,
                 "m2l_rhs_block": t.m2l_rhs_block, "rs_slab": list(t.rs_slab),
-                "m2l_by_parent": t.m2l_by_parent}
+                "m2l_by_parent": t.m2l_by_parent, "m2l_chunk": t.m2l_chunk}
 
     def tuning(self):
         """The plan's launch configuration (see ffmm_tuning)."""

@@ -314,7 +314,8 @@ ffmm_status ffmm_tuning_default(ffmm_tuning* t)
     t->rs_slab[1] = 32;
     t->rs_slab[2] = 32;
     t->rs_slab[3] = 16;
-    t->m2l_by_parent = 1;
+    t->m2l_by_parent = 2;
+    t->m2l_chunk = 48;
     g_last_error.clear();
     return FFMM_OK;
 }
@@ -469,7 +470,9 @@ static void check_tuning(const ffmm_tuning* t)
     for (int i = 0; i < 4; ++i)
         if (t->rs_slab[i] != 16 && t->rs_slab[i] != 32 && t->rs_slab[i] != 64)
             fail(FFMM_ERR_INVALID_ARG, "rs_slab entries must be 16, 32 or 64");
-    if (t->m2l_by_parent != 0 && t->m2l_by_parent != 1) fail(FFMM_ERR_INVALID_ARG, "m2l_by_parent must be 0 or 1");
+    if (t->m2l_by_parent < 0 || t->m2l_by_parent > 2) fail(FFMM_ERR_INVALID_ARG, "m2l_by_parent must be 0, 1 or 2");
+    if (t->m2l_chunk != 32 && t->m2l_chunk != 48 && t->m2l_chunk != 64)
+        fail(FFMM_ERR_INVALID_ARG, "m2l_chunk must be 32, 48 or 64");
 }
 
 ffmm_status ffmm_plan_set_tuning(ffmm_plan* p, const ffmm_tuning* t)
@@ -537,7 +540,8 @@ ffmm_status ffmm_plan_autotune(ffmm_plan* p, const void* d_q, void* d_out, int32
             }
         };
         try_field(&cur.near_stream, {1, 0});
-        try_field(&cur.m2l_by_parent, {1, 0});
+        try_field(&cur.m2l_by_parent, {2, 1, 0});
+        if (p->prec == FFMM_FP32 && cur.m2l_by_parent == 2) try_field(&cur.m2l_chunk, {48, 64, 32});
         try_field(&cur.p2p_blocks_per_cu, {1, 2, 3, 4, 6, 8, 0});
         if (nrhs >= 2) try_field(&cur.m2l_rhs_block, nrhs >= 4 ? std::initializer_list<int32_t>{1, 2, 4}
                                                               : std::initializer_list<int32_t>{1, 2});

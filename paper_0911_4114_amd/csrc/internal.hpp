@@ -81,8 +81,8 @@ struct LevelData {
     int32_t* d_nphi = nullptr;
     void* dirs = nullptr;           // [K][3] real
     void* weights = nullptr;        // [K] real (leaf level)
-    int Kp = 0;                     // leaf level: K / 2 antipodal direction pairs
-    int32_t* pairs = nullptr;       // leaf level: [Kp][2] (k, k') with s_k' = -s_k
+    int Kp = 0;                     // K / 2 antipodal direction pairs
+    int32_t* pairs = nullptr;       // [Kp][2] (k, k') with s_k' = -s_k
     void* transfer = nullptr;       // [34][K] complex: T of the representative transfer vectors
     int32_t* tperm = nullptr;       // [16][K]: T_{g rep}(s_k) = T_rep(s_{tperm[g][k]})
     void* trans = nullptr;          // [8][K] complex: e^{i kappa s.(oct - 1/2) a_{l+1}} (l < L)
@@ -151,6 +151,8 @@ struct ffmm_plan {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ffmm_tuning tune{};             // launch configuration (ffmm_plan_set_tuning)
     int32_t* code_map = nullptr;    // [343] offset code -> 16 rep + g, -1 for the inner codes
+    int32_t* m2l_rows = nullptr;    // [27][27] LDS row of 2D + e (-1: neighbours), [316] 16 rep + g,
+                                    // [27][8] mask of the source octants far from target octant ot
     int device = 0;                 // HIP device the plan was created on
     int n_cu = 0;                   // compute units of the plan's device
     void* scratch1 = nullptr;       // resample workspaces

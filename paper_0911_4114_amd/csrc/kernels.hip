@@ -473,6 +473,147 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
 }
 
 // ------------------------------------------------------------------------------------------
+// M2L by parent pairs with the transfer functions of a chunk of directions in LDS (FP32): the sums
+// of m2lp_kernel, I_b(s) = sum M_b'(s) T_{2D + o' - o}(s) over the far child pairs (o, o') of each
+// parent pair (P, P' = P + D), with every T value read from LDS. A block takes CW antipodal
+// direction pairs (s, -s) and a Morton range of parents. It first gathers into LDS the values at
+// its CW directions s of all 316 transfer functions (from the 34 representatives through the
+// quadrature symmetry; Fig. SemiOctant); the values at -s need no second table, since
+// T_r0(-s) = T_{-r0}(s) and, in code order, the row of -r0 is 315 minus the row of r0. Then each
+// wave takes parents of the range in turn, one lane per direction pair, and serves both
+// directions of its pair from each scalar decision (target octant present, source octant
+// present and far), so that the per-pair bookkeeping is shared by twice the multiply-adds. The
+// table is read from memory once per block and reused by every parent and right-hand side.
+// Per parent: lane D < 27 holds neighbour slot D (first child, octant mask of its children);
+// per occupied neighbour, a [27][27] table gives the LDS row of 2D + e (-1 where the boxes are
+// neighbours) and a [27][8] table the source octants far from each target octant.
+// ------------------------------------------------------------------------------------------
+constexpr int kTW = 16;   // waves per block of m2lt_kernel
+
+template <int CW>
+__global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
+    int K, int Kp, int nranges, int64_t np, const int32_t* __restrict__ pslots,
+    const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_count,
+    const int32_t* __restrict__ octant, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ pairs, const int32_t* __restrict__ tperm,
+    const float2* __restrict__ T, const float2* __restrict__ M, float2* __restrict__ out,
+    int64_t nb, int nrhs)
+{
+    static_assert(CW <= kWave && CW % 16 == 0, "chunk width");
+    __shared__ float2 Ts[kNumOffsets][CW];
+    __shared__ int s_next;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int chunk = (int)(lb / (unsigned)nranges), range = (int)(lb % (unsigned)nranges);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int pi = chunk * CW + lane;
+    const bool pvalid = lane < CW && pi < Kp;
+    // idle lanes work on the first pair and store nothing
+    const int k1 = pairs[2 * (pvalid ? pi : 0)], k2 = pairs[2 * (pvalid ? pi : 0) + 1];
+    const int cl = lane < CW ? lane : CW - 1;
+    // T_{g rep}(s_k1) = T_rep(s_{tperm[g][k1]}) of every transfer vector, row t of the table
+    const int32_t* row_tix = rows + 27 * 27;
+    const int32_t* farm = rows + 27 * 27 + kNumOffsets;
+    constexpr int kRowsPerWave = (kNumOffsets + kTW - 1) / kTW;
+#pragma unroll 5
+    for (int j = 0; j < kRowsPerWave; ++j) {
+        const int t = j * kTW + w;
+        if (t < kNumOffsets) {
+            const int tx = row_tix[t];
+            const float2 v = T[(int64_t)(tx >> 4) * K + tperm[(int64_t)(tx & (kNumSym - 1)) * K + k1]];
+            if (lane < CW) Ts[t][lane] = v;
+        }
+    }
+    if (threadIdx.x == 0) s_next = 0;
+    __syncthreads();
+    const int64_t pb = np * range / nranges, pe = np * (range + 1) / nranges;
+    const int64_t plane = nb * (int64_t)K;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(&s_next, 1);
+        item = __builtin_amdgcn_readfirstlane(item);   // every lane is active here: lane 0's value
+        const int64_t P = pb + item;
+        if (P >= pe) break;
+        const int tb = child_start[P], tn = child_count[P];
+        // lane D: neighbour slot D (the centre slot, P itself, has no far pairs)
+        int sb = 0, sm = 0;
+        bool occ_l = false;
+        if (lane < 27 && lane != 13) {
+            const int Pn = pslots[P * 27 + lane];
+            if (Pn >= 0) {
+                occ_l = true;
+                sb = child_start[Pn];
+                const int sn = child_count[Pn];
+                for (int i = 0; i < sn; ++i) sm |= 1 << octant[sb + i];
+            }
+        }
+        const uint64_t occ0 = __ballot(occ_l);
+        const int ot_l = lane < tn ? octant[tb + lane] : -1;
+        int tm = 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) tm |= (__ballot(ot_l == o) != 0 ? 1 : 0) << o;
+        for (int r = 0; r < nrhs; ++r) {
+            const float2* Mr = M + (int64_t)r * plane;
+            float2 acc[8][2];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) acc[o][0] = acc[o][1] = make_float2(0.f, 0.f);
+            uint64_t occ = occ0;
+            while (occ) {
+                const int D = __builtin_ctzll(occ);
+                occ &= occ - 1;
+                const int sbD = __builtin_amdgcn_readlane(sb, D);
+                const int smD = __builtin_amdgcn_readlane(sm, D);
+                const int32_t* pr = rows + 27 * D;
+                const int32_t* fm = farm + 8 * D;
+                // source signatures of the present octants at s and -s
+                float2 ms[8][2];
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    ms[o][0] = ms[o][1] = make_float2(0.f, 0.f);
+                    if ((smD >> o) & 1) {
+                        const int ci = sbD + __builtin_popcount(smD & ((1 << o) - 1));
+                        const float2* mp = Mr + (int64_t)ci * K;
+                        ms[o][0] = mp[k1];
+                        ms[o][1] = mp[k2];
+                    }
+                }
+                int rr[27];
+#pragma unroll
+                for (int e = 0; e < 27; ++e) rr[e] = pr[e];
+                // per present target octant, the present source octants far from it
+#pragma unroll
+                for (int ot = 0; ot < 8; ++ot) {
+                    if (!((tm >> ot) & 1)) continue;
+                    const int m = fm[ot] & smD;
+                    if (!m) continue;
+#pragma unroll
+                    for (int os = 0; os < 8; ++os) {
+                        if (!((m >> os) & 1)) continue;
+                        __asm__ __volatile__("");
+                        const int e = ((os & 1) - (ot & 1) + 1) + 3 * (((os >> 1) & 1) - ((ot >> 1) & 1) + 1) +
+                                      9 * (((os >> 2) & 1) - ((ot >> 2) & 1) + 1);
+                        const int row = rr[e];
+                        cmac(acc[ot][0], ms[os][0], Ts[row][cl]);
+                        cmac(acc[ot][1], ms[os][1], Ts[kNumOffsets - 1 - row][cl]);
+                    }
+                }
+            }
+            if (pvalid)
+                for (int i = 0; i < tn; ++i) {
+                    const int c = tb + i;
+                    const int o = __builtin_amdgcn_readfirstlane(octant[c]);
+                    float2* op = out + (int64_t)r * plane + (int64_t)c * K;
+#pragma unroll
+                    for (int oo = 0; oo < 8; ++oo)
+                        if (oo == o) {
+                            op[k1] = acc[oo][0];
+                            op[k2] = acc[oo][1];
+                        }
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // L2P (far part of eqn. FMM_FinalStep): phi_i += sum_k w_k L_b(s_k) e^{i kappa s_k.(c_b - x_i)};
 // with GRAD the gradient with respect to x_i, sum_k w_k L_b(s_k) (-i kappa s_k) e^{...}.
 // One wave per leaf box (four per block), one lane per target point; the directions are taken in
@@ -1043,6 +1184,27 @@ void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
             LevelData& Lv = p->lev[l];
             LevelData& Pv = p->lev[l - 1];
             const int kch = (Lv.K + 255) / 256;
+            if constexpr (sizeof(R) == 4) {
+                if (p->tune.m2l_by_parent == 2) {
+                    // chunks of CW antipodal direction pairs; ranges of parents so that the grid
+                    // is about one block per compute unit (a block holds most of a CU's LDS)
+                    const int cw = p->tune.m2l_chunk;
+                    const int64_t nch = (Lv.Kp + cw - 1) / cw;
+                    const int64_t nr = std::max<int64_t>(1, std::min<int64_t>(Pv.n, p->n_cu / std::max<int64_t>(nch, 1)));
+                    const dim3 grid((unsigned)(nch * nr));
+                    auto go = [&](auto kern) {
+                        hipLaunchKernelGGL(kern, grid, dim3(kWave * kTW), 0, s, Lv.K, Lv.Kp, (int)nr, Pv.n,
+                                           Pv.nb_slots, Pv.child_start, Pv.child_count, Lv.octant, p->m2l_rows,
+                                           Lv.pairs, Lv.tperm, (const float2*)Lv.transfer, (const float2*)Lv.sigM,
+                                           (float2*)Lv.sigL, Lv.n, nrhs);
+                    };
+                    if (cw == 64) go(m2lt_kernel<64>);
+                    else if (cw == 48) go(m2lt_kernel<48>);
+                    else go(m2lt_kernel<32>);
+                    FFMM_LAUNCH_CHECK();
+                    continue;
+                }
+            }
             if (p->tune.m2l_by_parent) {
                 const int rbp = rb >= 2 ? 2 : 1;
                 // 128-direction blocks where they leave fewer idle lanes than 256-direction ones

@@ -606,8 +606,8 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             }
         }
         upload_real<R>(p->arena, &L.dirs, dirs, s);
-        if (l == depth) {
-            upload_real<R>(p->arena, &L.weights, w, s);
+        if (l == depth) upload_real<R>(p->arena, &L.weights, w, s);
+        {
             // antipodal pairs: row theta_n at phi_m and row pi - theta_n (index N_theta/2 - n) at
             // phi_m + pi give s and -s; the rows have equal N_phi (Alg. Nphi takes the larger of
             // the two) and every N_phi is a multiple of 4, so all K directions pair up

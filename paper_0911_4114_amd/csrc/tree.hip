@@ -753,6 +753,43 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s)
         }
         p->code_map = p->arena.alloc_n<int32_t>(kNumCodes);
         FFMM_HIP(hipMemcpyAsync(p->code_map, map, sizeof(map), hipMemcpyHostToDevice, s));
+        // M2L with the transfer functions in LDS: the 316 transfer vectors as LDS rows in code
+        // order; per parent offset D and child offset e (both x + 3y + 9z of components + 1) the
+        // row of 2D + e (-1 where that vector joins neighbours), then per row its packed
+        // representative and symmetry (16 rep + g), then per D and target octant the mask of the
+        // source octants that are far from it
+        std::vector<int32_t> rows(27 * 27 + kNumOffsets + 27 * 8);
+        {
+            int32_t code_row[kNumCodes];
+            int r = 0;
+            for (int c = 0; c < kNumCodes; ++c) {
+                code_row[c] = map[c] >= 0 ? r : -1;
+                if (map[c] >= 0) rows[27 * 27 + r++] = map[c];
+            }
+            if (r != kNumOffsets) fail(FFMM_ERR_INTERNAL, "transfer vector count");
+            for (int D = 0; D < 27; ++D)
+                for (int e = 0; e < 27; ++e) {
+                    const int cx = 2 * (D % 3 - 1) + (e % 3 - 1) + 3;
+                    const int cy = 2 * ((D / 3) % 3 - 1) + ((e / 3) % 3 - 1) + 3;
+                    const int cz = 2 * (D / 9 - 1) + (e / 9 - 1) + 3;
+                    rows[27 * D + e] = code_row[cx + 7 * cy + 49 * cz];
+                }
+            // per D and target octant ot: bit os set where source octant os is far from ot
+            // (the vector 2D + os - ot is one of the 316)
+            for (int D = 0; D < 27; ++D)
+                for (int ot = 0; ot < 8; ++ot) {
+                    int m = 0;
+                    for (int os = 0; os < 8; ++os) {
+                        const int e = ((os & 1) - (ot & 1) + 1) + 3 * (((os >> 1) & 1) - ((ot >> 1) & 1) + 1) +
+                                      9 * (((os >> 2) & 1) - ((ot >> 2) & 1) + 1);
+                        if (rows[27 * D + e] >= 0) m |= 1 << os;
+                    }
+                    rows[27 * 27 + kNumOffsets + 8 * D + ot] = m;
+                }
+        }
+        p->m2l_rows = p->arena.alloc_n<int32_t>(rows.size());
+        FFMM_HIP(hipMemcpyAsync(p->m2l_rows, rows.data(), sizeof(int32_t) * rows.size(),
+                                hipMemcpyHostToDevice, s));
         FFMM_HIP(hipStreamSynchronize(s));
     } catch (...) {
         tmp.release();

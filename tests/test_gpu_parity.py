@@ -227,7 +227,7 @@ def test_fp32_stages_match_oracle(gpu):
     far_ref = np.empty(len(x), complex)
     far_ref[o.tree.perm] = st["far"]
     qd = dev_complex(q, fp32=True)
-    for by_parent in (1, 0):
+    for by_parent in (2, 1, 0):
         p.set_tuning(m2l_by_parent=by_parent)
         far = p.matvec_stages(qd, ff.STAGE_FAR).cpu().numpy().astype(complex)
         for l in range(2, 5):
@@ -242,3 +242,42 @@ def test_fp32_stages_match_oracle(gpu):
         e = np.abs(far - far_ref) / amp
         log("  by_parent %d far field: max err / amplitude %.2e" % (by_parent, e.max()))
         assert e.max() < TOL_FP32_BOX
+
+
+@pytest.mark.parametrize("name", ["cube4096", "sphere65k_d5", "ellipsoid3000"])
+def test_m2l_forms_agree(gpu, name):
+    """The M2L form with the transfer functions in LDS (form 2: antipodal direction pairs, chunks
+    of 32, 48 and 64 pairs, including a ragged last chunk) adds each interaction-list term in an
+    order that depends only on the tree, so its chunk width and right-hand-side blocking change no
+    bit; against the form that reads T per parent pair (form 1) it differs by FP32 rounding only.
+    FP32, three right-hand sides; every level's local signatures and the far field."""
+    gen, kappa, depth = CASES[name]
+    x = gen()
+    Q = wl.complex_normal(len(x), seed=21, nrhs=3)
+    log("m2l forms %s" % name)
+    p = ff.Plan(dev_points(x), kappa, 1e-4, precision="fp32", depth=depth, max_rhs=3,
+                best_effort=True)
+    info = p.info()
+    L = info["depth"]
+    assert any((info["K"][l] // 2) % 48 for l in range(2, L + 1))
+    qd = dev_complex(Q, fp32=True)
+    p.set_tuning(m2l_by_parent=1, m2l_rhs_block=1)
+    ref1 = p.matvec_stages(qd, ff.STAGE_FAR).cpu().numpy()
+    sig1 = {l: p.signature(1, l, rhs=2) for l in range(2, L + 1)}
+    ref2 = sig2 = None
+    for cw in (32, 48, 64):
+        for rb in (1, 2):
+            p.set_tuning(m2l_by_parent=2, m2l_chunk=cw, m2l_rhs_block=rb)
+            got = p.matvec_stages(qd, ff.STAGE_FAR).cpu().numpy()
+            sig = {l: p.signature(1, l, rhs=2) for l in range(2, L + 1)}
+            if ref2 is None:
+                ref2, sig2 = got, sig
+                for l in range(2, L + 1):
+                    box = np.max(np.abs(sig[l] - sig1[l]), axis=1) / np.max(np.abs(sig1[l]), axis=1)
+                    log("  L^%d form 2 vs 1: box-relative max %.2e" % (l, box.max()))
+                    assert box.max() < 1e-5, (l, box.max())
+                assert rel_l2(got, ref1) < 1e-5
+            else:
+                assert np.array_equal(got, ref2), (cw, rb)
+                for l in range(2, L + 1):
+                    assert np.array_equal(sig[l], sig2[l]), (cw, rb, l)
