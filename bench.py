@@ -47,6 +47,10 @@ def parse():
                     help="also run the volume workload: 2^12..2^22 points uniform in the unit cube, "
                          "kappa = 2 pi N^(1/3) / 2.52, FP32, eps 1e-4, automatic method and depth")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fast", action="store_true",
+                    help="skip the run with the opt-in FP32 near-field distance and phase")
+    ap.add_argument("--no-cube", action="store_true",
+                    help="skip the 4096-point cube (kappa 8 pi, depth 3, FP64, eps 1e-6)")
     ap.add_argument("--serial", action="store_true",
                     help="run P2P in order on the calling stream (no overlap), so that a kernel "
                          "trace shows every kernel alone")
@@ -57,6 +61,68 @@ def parse():
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the autograd run (2^18 sphere points, kappa 88, loss sum |phi - phi_t|^2)")
     return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+class omp_threads:
+    """Limit the OpenMP threads of the oracle's C sums (libgomp) inside a with block."""
+
+    def __init__(self, n):
+        import ctypes
+        self.n = n
+        self.gomp = ctypes.CDLL("libgomp.so.1")
+        self.old = None
+
+    def __enter__(self):
+        self.old = self.gomp.omp_get_max_threads()
+        self.gomp.omp_set_num_threads(self.n)
+
+    def __exit__(self, *exc):
+        self.gomp.omp_set_num_threads(self.old)
+
+
+def oracle_ffmm_timing(eps):
+    """Seconds per matvec of the oracle's CPU Fourier-basis FMM (FP64, NumPy) on 2^16 points on
+    the unit sphere at kappa = 177 (2^16 / 2^20)^(1/2) (the benchmark's points per wavelength),
+    with every host core available to its libraries and with one."""
+    from threadpoolctl import threadpool_limits
+    from oracle.ffmm import Plan as OPlan
+    from paper_0911_4114_amd import workloads as wl
+    n = 1 << 16
+    kappa = 177.0 * (n / 2.0 ** 20) ** 0.5
+    x = wl.sphere_points(n, seed=0)
+    q = wl.complex_normal(n, seed=1)
+    t0 = time.perf_counter()
+    op = OPlan(x, kappa, eps)
+    for l in range(2, op.depth + 1):
+        op.table(l)
+    setup = time.perf_counter() - t0
+    res = {"n": n, "kappa": kappa, "eps": eps, "depth": op.depth, "setup_s": setup,
+           "unit": "Mpoints/s", "kind": "oracle FMM"}
+    for key, lim in (("all_cores", None), ("one_core", 1)):
+        with threadpool_limits(lim):
+            t0 = time.perf_counter()
+            op.matvec(q)
+            dt = time.perf_counter() - t0
+        res[key] = {"matvec_s": dt, "value": n / dt / 1e6,
+                    "cores": len(os.sched_getaffinity(0)) if lim is None else 1}
+    return res
+
+
+def workload_label(n, kappa, eps, info):
+    L = info["depth"]
+    return ("sphere N=%d kappa=%g FP32 eps=%g nrhs=1, depth %d (leaves of up to %d points: the "
+            "leaf level of depth %d, where every leaf holds <= 64, is in the low-frequency "
+            "breakdown for eps in FP32)" % (n, kappa, eps, L, info.get("max_leaf_points", 0), L + 1))
 
 
 def timed(fn, steps, warmup):
@@ -74,29 +140,62 @@ def timed(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+# Peaks (MI355X published figures): FP32 vector (packed) and FP64 vector FLOP/s, the FP32
+# transcendental rate (sine, cosine, reciprocal square root issue at a quarter of the lane rate:
+# 256 CUs x 16 lanes x 2.4 GHz) and HBM bandwidth.
+TRANS_PEAK_TPS = 256 * 16 * 2.4e9 / 1e12
+
+
 def stage_work(info, stage):
-    """Algorithmic work of one launch group of a stage (per right-hand side):
-    returns (bound, amount, unit) with amount in GB or TFLOP."""
+    """Algorithmic work of one stage per right-hand side: dict with FLOPs, transcendental
+    evaluations and HBM bytes, and the FLOP peak that applies (TFLOP/s)."""
     L = info["depth"]
     n = info["n_points"]
     cs = 8 if info["precision"] == 1 else 16
+    rs = cs // 2
+    K, nb = info["K"], info["n_boxes"]
+    kp = K[L] // 2
+    fpk = FP32_PEAK_TFLOPS if info["precision"] == 1 else FP64_PEAK_TFLOPS
+    w = {"flops": 0.0, "trans": 0.0, "bytes": 0.0, "peak": fpk}
     if stage in ("m2l", "leaf_m2l"):
         lv = [L] if stage == "leaf_m2l" else range(2, L + 1)
-        flops = sum(8.0 * info["n_ilist"][l] * info["K"][l] for l in lv)
-        return "alu", flops / 1e12, "TFLOP"
-    if stage == "p2m":
-        return "alu", 14.0 * n * info["K"][L] / 1e12, "TFLOP"
-    if stage == "l2p":
-        return "alu", 16.0 * n * info["K"][L] / 1e12, "TFLOP"
-    if stage == "p2p":
-        return "alu", 26.0 * info["n_near_pairs"] / 1e12, "TFLOP"
-    if stage in ("m2m", "l2l"):
-        byt = sum(cs * (info["n_boxes"][l] * info["K"][l] + info["n_boxes"][l - 1] * info["K"][l - 1])
-                  for l in range(3, L + 1))
-        return "hbm", byt / 1e9, "GB"
-    if stage in ("gather", "scatter"):
-        return "hbm", (2 * cs + 8) * n / 1e9, "GB"
-    return "hbm", 0.0, "GB"
+        w["flops"] = sum(8.0 * info["n_ilist"][l] * K[l] for l in lv)
+        w["bytes"] = sum(cs * (2.0 * nb[l] * K[l] + 34.0 * K[l]) for l in lv)
+    elif stage in ("p2m", "l2p"):
+        # per (point, antipodal direction pair): phase 3 FMA, one sine and one cosine, 4 FMA
+        w["flops"] = 14.0 * n * kp
+        w["trans"] = 2.0 * n * kp
+        w["bytes"] = n * (3 * rs + 2 * cs) + cs * nb[L] * K[L]
+    elif stage == "p2p":
+        # per ordered pair: FP64 differences, R^2, R and the phase reduction; FP32 1/R, complex
+        # MAC; reciprocal square root, sine and cosine
+        w["flops"] = 26.0 * info["n_near_pairs"]
+        w["trans"] = 3.0 * info["n_near_pairs"]
+        w["bytes"] = n * (24 + 2 * cs)
+        w["peak"] = FP64_PEAK_TFLOPS
+    elif stage == "m2m":
+        w["bytes"] = sum(cs * (nb[l] * K[l] + nb[l - 1] * K[l - 1]) for l in range(3, L + 1))
+    elif stage == "l2l":
+        w["bytes"] = sum(cs * (nb[l] * K[l] + 2.0 * nb[l + 1] * K[l + 1]) for l in range(2, L))
+    elif stage == "gather":
+        w["bytes"] = (2 * cs + 8) * n
+    elif stage == "scatter":
+        w["bytes"] = (3 * cs + 8) * n
+    return w
+
+
+def stage_roofline(info, stage, ms):
+    """Roofline time of a stage (the largest of FLOPs / peak, transcendentals / rate and bytes /
+    HBM bandwidth), its bound and the achieved rates against the peaks."""
+    w = stage_work(info, stage)
+    t = {"alu": w["flops"] / (w["peak"] * 1e12), "trans": w["trans"] / (TRANS_PEAK_TPS * 1e12),
+         "hbm": w["bytes"] / (HBM_PEAK_GBS * 1e9)}
+    bound = max(t, key=t.get)
+    s = ms * 1e-3
+    return {"ms": round(ms, 4), "bound": bound, "roofline_ms": round(t[bound] * 1e3, 4),
+            "frac": t[bound] / s if s > 0 else None,
+            "tflops": w["flops"] / s / 1e12, "flops_peak": w["peak"],
+            "ttrans_per_s": w["trans"] / s / 1e12, "gbs": w["bytes"] / s / 1e9}
 
 
 # HBM traffic of the dominant kernel: FETCH_SIZE and WRITE_SIZE per dispatch from rocprofv3 --pmc,
@@ -194,24 +293,29 @@ def main():
     cand["m2l"] = {"ms_per_step": m2l_total,
                    "launches_per_step": stages["m2l"]["launches_per_step"] + stages["leaf_m2l"]["launches_per_step"]}
     dom = max(cand, key=lambda k: cand[k]["ms_per_step"])
-    bound, amount, unit = stage_work(info, dom)
     nlaunch = max(cand[dom]["launches_per_step"], 1.0)
     per_launch_ms = cand[dom]["ms_per_step"] / nlaunch
-    per_launch_amount = amount / nlaunch
-    if bound == "hbm":
-        achieved = per_launch_amount / (per_launch_ms * 1e-3)
+    wd = stage_work(info, dom)
+    if dom in ("m2m", "l2l", "gather", "scatter"):
+        achieved = wd["bytes"] / nlaunch / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     else:
-        achieved = per_launch_amount / (per_launch_ms * 1e-3)
-        # P2P carries FP64 distance/phase arithmetic: priced against the FP64 vector peak (the
-        # same lane rate as non-packed FP32); the other ALU stages against the FP32 vector peak
-        peak = FP64_PEAK_TFLOPS if dom == "p2p" else FP32_PEAK_TFLOPS
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
+        # the FLOP peak of the stage's precision: P2P carries FP64 distance and phase arithmetic
+        # (FP64 vector peak), the other ALU stages FP32 vector arithmetic
+        achieved = wd["flops"] / nlaunch / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": wd["peak"], "unit": "TFLOP/s",
+                "frac": achieved / wd["peak"], "traffic": None,
+                "trans_frac": wd["trans"] / nlaunch / (per_launch_ms * 1e-3) / 1e12 / TRANS_PEAK_TPS}
     roof["stage"] = dom
     roof["launch_ms"] = per_launch_ms
     roof["traffic"] = measured_traffic(dom, args)
+    # every stage against its own roofline, and the whole matvec: the sum of the stages'
+    # roofline times over the measured matvec time
+    stage_roof = {k: stage_roofline(info, k, v["ms_per_step"]) for k, v in cand.items()}
+    roof_sum_ms = sum(v["roofline_ms"] for v in stage_roof.values())
+    matvec_roof = {"roofline_ms": roof_sum_ms, "measured_ms": ms, "frac": roof_sum_ms / ms,
+                   "stages_alone_ms": sum(v["ms"] for v in stage_roof.values())}
 
     # accuracy against the oracle's direct sum on a subset of targets (host FP64)
     out = plan.matvec(q32).cpu().numpy().astype(np.complex128)
@@ -229,8 +333,21 @@ def main():
         cpu = {"value": len(tg) / cpu_s / 1e6, "unit": "Mpoints/s", "cores": cores,
                "kind": "oracle",
                "sample": "oracle direct sum (C/OpenMP FP64): %d of %d targets against all %d sources, %.1f s"
-                         % (len(tg), n, n, cpu_s)}
-        log("fp32 rel err %.3e; cpu %.4f Mpoints/s" % (rel_err, cpu["value"]))
+                         % (len(tg), n, n, cpu_s),
+               "cpu_model": cpu_model()}
+        # the same sum on one host core (OpenMP limited to one thread), 256 targets
+        t1 = time.perf_counter()
+        with omp_threads(1):
+            direct.matvec(x, q, args.kappa, targets=tg[:256])
+        s1 = time.perf_counter() - t1
+        cpu["one_core"] = {"value": 256 / s1 / 1e6, "unit": "Mpoints/s", "cores": 1,
+                           "sample": "oracle direct sum, 256 of %d targets, %.1f s" % (n, s1)}
+        # the oracle's Fourier-basis FMM (CPU FP64, NumPy) per matvec on a reduced sphere of the
+        # same points per wavelength: 2^16 points, kappa = 177 (2^16 / 2^20)^(1/2); transfer
+        # tables built before the timed call (setup)
+        cpu["ffmm"] = oracle_ffmm_timing(args.eps)
+        log("fp32 rel err %.3e; cpu %.4f Mpoints/s (one core %.5f; oracle FMM %s)"
+            % (rel_err, cpu["value"], cpu["one_core"]["value"], cpu["ffmm"]))
 
     batched = None
     if not args.no_batched:
@@ -243,10 +360,10 @@ def main():
         # the library's autotuner picks the launch configuration for 16 right-hand sides (setup)
         t0 = time.perf_counter()
         tuned = pb.autotune(qb)
-        tune_s = time.perf_counter() - t0
+        tune_b_s = time.perf_counter() - t0
         msb = timed(lambda: pb.matvec(qb), max(3, args.steps // 2), 1)
         batched = {"nrhs": nb_rhs, "value": n * nb_rhs / (msb * 1e-3) / 1e6, "ms_per_step": msb,
-                   "tuning": tuned, "autotune_s": tune_s}
+                   "tuning": tuned, "autotune_s": tune_b_s}
         if not args.no_cpu:
             ob = pb.matvec(qb)[3].cpu().numpy().astype(np.complex128)
             qh = wl.plane_wave_charges(x, args.kappa, nb_rhs, seed=2)[3]
@@ -360,6 +477,59 @@ def main():
         del pg
         torch.cuda.empty_cache()
 
+    # the FP32 near field with the opt-in FP32 distance and phase (fast_near_phase), beside the
+    # default FP64 distance and phase: time and error of the same workload
+    fast = None
+    if not args.no_fast:
+        pf = ff.Plan(xt, args.kappa, args.eps, precision="fp32", depth=args.depth or None,
+                     fast_near_phase=True)
+        pf.set_tuning(**plan_tuning)
+        msf = timed(lambda: pf.matvec(q32), args.steps, args.warmup)
+        pf.set_tuning(near_stream=0, p2p_blocks_per_cu=0)
+        pf.profile(True)
+        for _ in range(3):
+            pf.matvec_stages(q32, ff.STAGE_NEAR)
+        p2p_fast = pf.profile_read()["p2p"][0] / 3
+        pf.profile(False)
+        pf.set_tuning(**plan_tuning)
+        fast = {"ms_per_step": msf, "value": n / (msf * 1e-3) / 1e6, "p2p_ms": p2p_fast}
+        if not args.no_cpu:
+            of = pf.matvec(q32).cpu().numpy().astype(np.complex128)
+            fast["rel_err"] = float(np.linalg.norm(of[tg] - ref) / np.linalg.norm(ref))
+        log("fast near phase: %s" % fast)
+        del pf
+        torch.cuda.empty_cache()
+
+    # the plain FP64 workload of the paper's volume shape: 4096 points uniform in the unit cube,
+    # kappa = 8 pi, depth 3, eps 1e-6, against the full direct sum (and the oracle's CPU FMM)
+    cube = None
+    if not args.no_cube:
+        nc, kc = 4096, 8.0 * np.pi
+        xc = wl.cube_points(nc, seed=0)
+        qc = wl.complex_normal(nc, seed=1)
+        pc = ff.Plan(torch.as_tensor(xc, dtype=torch.float64, device=dev), kc, 1e-6,
+                     precision="fp64", depth=3, best_effort=True)
+        qct = torch.as_tensor(qc, dtype=torch.complex128, device=dev)
+        msc = timed(lambda: pc.matvec(qct), args.steps, args.warmup)
+        ic = pc.info()
+        cube = {"n": nc, "kappa": kc, "depth": 3, "eps": 1e-6, "ms_per_step": msc,
+                "value": nc / (msc * 1e-3) / 1e6, "predicted_err": max(ic["predicted_err"][2:4])}
+        if not args.no_cpu:
+            from oracle.ffmm import Plan as OPlan
+            oc = pc.matvec(qct).cpu().numpy()
+            rc = direct.matvec(xc, qc, kc)
+            cube["rel_err"] = float(np.linalg.norm(oc - rc) / np.linalg.norm(rc))
+            op = OPlan(xc, kc, 1e-6, depth=3)
+            for l in range(2, 4):
+                op.table(l)
+            t0 = time.perf_counter()
+            oo = op.matvec(qc)
+            cube["cpu_ffmm_s"] = time.perf_counter() - t0
+            cube["cpu_ffmm_rel_err"] = float(np.linalg.norm(oo - rc) / np.linalg.norm(rc))
+        log("cube: %s" % cube)
+        del pc
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         del plan
@@ -392,7 +562,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sphere N=%d kappa=%g leaf<=64 FP32 eps=%g nrhs=1" % (n, args.kappa, args.eps),
+        "config": {"workload": workload_label(n, args.kappa, args.eps, info),
                    "n": n, "kappa": args.kappa, "eps": args.eps, "nrhs": 1,
                    "depth": info["depth"], "ell": info["ell"][2:], "K": info["K"][2:],
                    "boxes": info["n_boxes"][2:], "ilist": info["n_ilist"][2:],
@@ -402,6 +572,10 @@ def main():
         "setup_s": setup_s,
         "tuning": plan_tuning,
         "autotune_s": tune_s,
+        "stages": stage_roof,
+        "matvec_roofline": matvec_roof,
+        "fast_near_phase": fast,
+        "cube": cube,
         "stages_ms": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
         "fp64": fp64,
         "batched": batched,

@@ -132,6 +132,8 @@ typedef struct {
     int64_t device_bytes;                /* device memory held by the plan */
     int32_t max_rhs;
     int32_t method;                      /* FFMM_METHOD_FMM or FFMM_METHOD_DIRECT (depth 0) */
+    int32_t max_leaf_count;              /* points in the fullest leaf (FMM plans) */
+    int32_t reserved;
 } ffmm_plan_info;
 
 /* Fill *o with the defaults listed above. o must not be NULL. */

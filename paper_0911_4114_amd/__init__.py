@@ -99,7 +99,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_ilist", ctypes.c_int64 * MAX_LEVELS),
                 ("predicted_err", ctypes.c_double * MAX_LEVELS),
                 ("n_near_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("max_rhs", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("max_leaf_count", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -329,7 +330,7 @@ class Plan:
             "n_boxes": list(pi.n_boxes[: d + 1]), "n_ilist": list(pi.n_ilist[: d + 1]),
             "predicted_err": list(pi.predicted_err[: d + 1]), "n_near_pairs": pi.n_near_pairs,
             "device_bytes": pi.device_bytes, "max_rhs": pi.max_rhs,
-            "method": ("fmm", "direct")[pi.method],
+            "method": ("fmm", "direct")[pi.method], "max_leaf_points": pi.max_leaf_count,
         }
 
     def perm(self):

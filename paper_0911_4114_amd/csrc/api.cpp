@@ -597,6 +597,7 @@ ffmm_status ffmm_plan_info_get(const ffmm_plan* p, ffmm_plan_info* out)
         out->device_bytes = (int64_t)p->arena.bytes;
         out->max_rhs = p->opt.max_rhs;
         out->method = p->direct ? FFMM_METHOD_DIRECT : FFMM_METHOD_FMM;
+        out->max_leaf_count = p->max_leaf_count;
     });
 }
 

@@ -42,3 +42,22 @@ def test_bench_refuses_more_than_one_gpu(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_stage_roofline_takes_the_largest_bound():
+    """Each stage's roofline time is the largest of FLOPs / peak, transcendentals / rate and
+    bytes / HBM bandwidth, and its fraction is that time over the measured one."""
+    bench = load_bench()
+    info = {"depth": 3, "n_points": 1000, "precision": 1, "K": [0, 0, 400, 100],
+            "n_boxes": [1, 8, 64, 512], "n_ilist": [0, 0, 200, 5000], "n_near_pairs": 10 ** 6}
+    for st in ("p2m", "l2p", "p2p", "m2l", "m2m", "l2l", "gather", "scatter"):
+        w = bench.stage_work(info, st)
+        r = bench.stage_roofline(info, st, 1.0)
+        t = {"alu": w["flops"] / (w["peak"] * 1e12), "trans": w["trans"] / (bench.TRANS_PEAK_TPS * 1e12),
+             "hbm": w["bytes"] / (bench.HBM_PEAK_GBS * 1e9)}
+        assert r["bound"] == max(t, key=t.get)
+        assert r["roofline_ms"] == pytest.approx(round(1e3 * max(t.values()), 4), abs=1e-4)
+        assert r["frac"] == pytest.approx(max(t.values()) / 1e-3)
+    # M2L: 8 flops per interaction-list entry and direction over every level
+    assert bench.stage_work(info, "m2l")["flops"] == 8.0 * (200 * 400 + 5000 * 100)
+    assert bench.stage_work(info, "leaf_m2l")["flops"] == 8.0 * 5000 * 100
