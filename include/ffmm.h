@@ -354,6 +354,14 @@ ffmm_status ffmm_plan_get_level(const ffmm_plan* plan, int32_t l, uint64_t* keys
                                 int32_t* start, int32_t* count, int32_t* il_ptr, int32_t* il_src,
                                 int32_t* il_code, int32_t* nb_ptr, int32_t* nb_src);
 
+/*
+ * Error studies: restrict the transfer pass (M2L, Section 2) of later calls to the levels whose
+ * bit is set in level_mask (bit l = level l; all levels by default, mask 0xffffffff). The far
+ * field then holds only the contributions of the interaction lists of those levels, passed down
+ * the tree as usual; the local expansions of the other levels start from zero. Not for products.
+ */
+ffmm_status ffmm_plan_set_m2l_levels(ffmm_plan* plan, uint32_t level_mask);
+
 /* N_phi(theta_n) of level l's quadrature: host int32[ntheta/2 + 1]. */
 ffmm_status ffmm_plan_get_nphi(const ffmm_plan* plan, int32_t l, int32_t* nphi);
 

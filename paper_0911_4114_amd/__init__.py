@@ -121,6 +121,7 @@ _SIGS = {
     "ffmm_position_gradient": [_P, _P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec": [_P, _P, _P, ctypes.c_int32, _P],
     "ffmm_matvec_static": [_P, _P, _P, ctypes.c_int32, _P],
+    "ffmm_plan_set_m2l_levels": [_P, ctypes.c_uint32],
     "ffmm_matvec_stages": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "ffmm_adjoint": [_P, _P, _P, ctypes.c_int32, _P],
     "ffmm_field_gradient": [_P, _P, _P, ctypes.c_int32, _P],
@@ -373,6 +374,11 @@ class Plan:
         if l == info["depth"]:
             out["nb_src"] = out["nb_src"][: out["nb_ptr"][-1]]
         return out
+
+    def set_m2l_levels(self, levels=None):
+        """Error studies: run the transfer pass only at the given levels (None: all levels)."""
+        mask = 0xffffffff if levels is None else sum(1 << int(l) for l in levels)
+        _check(load_library().ffmm_plan_set_m2l_levels(self._h, mask))
 
     def nphi(self, l):
         info = self.info()

@@ -710,6 +710,14 @@ ffmm_status ffmm_plan_get_level(const ffmm_plan* p, int32_t l, uint64_t* keys, i
     });
 }
 
+ffmm_status ffmm_plan_set_m2l_levels(ffmm_plan* p, uint32_t level_mask)
+{
+    return guarded([&] {
+        if (!p) fail(FFMM_ERR_INVALID_ARG, "plan is NULL");
+        p->m2l_levels = level_mask;
+    });
+}
+
 ffmm_status ffmm_plan_get_nphi(const ffmm_plan* p, int32_t l, int32_t* nphi)
 {
     return guarded([&] {

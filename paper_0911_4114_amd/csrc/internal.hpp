@@ -160,6 +160,7 @@ struct ffmm_plan {
     size_t scratch1_bytes = 0, scratch2_bytes = 0;
     std::vector<double> predicted;  // per level
     bool has_run = false;
+    uint32_t m2l_levels = 0xffffffffu;   // ffmm_plan_set_m2l_levels
     // stage timing (ffmm_profile_enable)
     bool profile = false;
     struct EventPair {

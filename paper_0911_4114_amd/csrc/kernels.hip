@@ -1183,6 +1183,11 @@ void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
             StageScope sc(p, l == L ? FFMM_PROF_LEAF_M2L : FFMM_PROF_M2L, s);
             LevelData& Lv = p->lev[l];
             LevelData& Pv = p->lev[l - 1];
+            if (!((p->m2l_levels >> l) & 1u)) {
+                // error studies: this level's interaction lists contribute nothing
+                FFMM_HIP(hipMemsetAsync(Lv.sigL, 0, sizeof(C) * (size_t)nrhs * Lv.n * Lv.K, s));
+                continue;
+            }
             const int kch = (Lv.K + 255) / 256;
             if constexpr (sizeof(R) == 4) {
                 if (p->tune.m2l_by_parent == 2) {
