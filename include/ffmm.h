@@ -261,8 +261,9 @@ ffmm_status ffmm_profile_read(ffmm_plan* plan, double* ms, int64_t* calls);
  */
 typedef struct {
     int32_t struct_size;        /* sizeof(ffmm_tuning); set by ffmm_tuning_default */
-    int32_t near_stream;        /* 1 (default): P2P runs on a second stream of the plan, overlapping
-                                   the far-field stages; 0: every stage in order on the caller's stream */
+    int32_t near_stream;        /* 2 (default): P2P runs on a second stream of the plan, forked before
+                                   P2M and overlapping the far-field stages; 1: the same, forked after
+                                   the upward pass; 0: every stage in order on the caller's stream */
     int32_t p2p_blocks_per_cu;  /* P2P blocks per compute unit, each looping over leaves (1..16);
                                    0 (default) = one block per four leaves */
     int32_t m2l_rhs_block;      /* right-hand sides sharing each transfer-function read in M2L:
@@ -278,9 +279,10 @@ typedef struct {
                                    faster than 0 at the leaves of a volume distribution); 0: one
                                    target box per block over its interaction list. Forms 1 and 2
                                    give the same bits. */
-    int32_t m2l_chunk;          /* directions per block of M2L form 2: 64 (158 KB of LDS, one block
-                                   per compute unit), 48 (default; 121 KB, leaving room for a P2P
-                                   block beside it) or 32 (81 KB) */
+    int32_t m2l_chunk;          /* antipodal direction pairs per block of M2L form 2: 64 (default;
+                                   158 KB of LDS, one block per compute unit, so that no P2P block of
+                                   a persistent P2P grid fits beside it), 48 (121 KB, leaving room
+                                   for one) or 32 (81 KB) */
 } ffmm_tuning;
 
 /* Fill *t with the defaults listed above. t must not be NULL. */
@@ -293,12 +295,14 @@ ffmm_status ffmm_plan_get_tuning(const ffmm_plan* plan, ffmm_tuning* out);
 
 /*
  * Autotuner: time matvecs of the nrhs right-hand sides at d_q (device, layout of ffmm_matvec)
- * under candidate launch configurations, by coordinate descent over the fields of ffmm_tuning
- * starting from the plan's current one, then a confirmation in which the starting configuration,
- * the descent's choice and that choice with the other P2P placement are timed in turn over three
- * rounds; the fastest is kept on the plan (also copied to *best when best is not NULL). d_out
- * receives the products (its contents are those of the last candidate). Runs about 28
- * configurations x 6 matvecs, ordered on hip_stream; synchronises it.
+ * under candidate launch configurations: the P2P placement (near_stream, p2p_blocks_per_cu) and
+ * the M2L chunk width over a joint grid (they compete for the same LDS), then coordinate descent
+ * over the other fields and the P2P grid once more, then a confirmation in which the starting
+ * configuration, the search's choice and that choice with the other P2P fork point are timed in
+ * turn over three rounds; the fastest is kept on the plan (also copied to *best when best is not
+ * NULL). Each configuration is timed as the best of three groups of three back-to-back
+ * products after one warm-up. d_out receives the products (its contents are those of the last
+ * candidate). Runs about 60 configurations x 10 matvecs, ordered on hip_stream; synchronises it.
  */
 ffmm_status ffmm_plan_autotune(ffmm_plan* plan, const void* d_q, void* d_out, int32_t nrhs,
                                void* hip_stream, ffmm_tuning* best);

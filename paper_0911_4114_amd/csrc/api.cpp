@@ -307,7 +307,7 @@ ffmm_status ffmm_tuning_default(ffmm_tuning* t)
     }
     std::memset(t, 0, sizeof(*t));
     t->struct_size = (int32_t)sizeof(ffmm_tuning);
-    t->near_stream = 1;
+    t->near_stream = 2;
     t->p2p_blocks_per_cu = 0;
     t->m2l_rhs_block = 0;
     t->rs_slab[0] = 16;
@@ -315,7 +315,7 @@ ffmm_status ffmm_tuning_default(ffmm_tuning* t)
     t->rs_slab[2] = 32;
     t->rs_slab[3] = 16;
     t->m2l_by_parent = 2;
-    t->m2l_chunk = 48;
+    t->m2l_chunk = 64;
     g_last_error.clear();
     return FFMM_OK;
 }
@@ -462,7 +462,7 @@ static void check_tuning(const ffmm_tuning* t)
     if (!t) fail(FFMM_ERR_INVALID_ARG, "tuning is NULL");
     if (t->struct_size != (int32_t)sizeof(ffmm_tuning))
         fail(FFMM_ERR_INVALID_ARG, "tuning.struct_size does not match this library");
-    if (t->near_stream != 0 && t->near_stream != 1) fail(FFMM_ERR_INVALID_ARG, "near_stream must be 0 or 1");
+    if (t->near_stream < 0 || t->near_stream > 2) fail(FFMM_ERR_INVALID_ARG, "near_stream must be 0, 1 or 2");
     if (t->p2p_blocks_per_cu < 0 || t->p2p_blocks_per_cu > 16)
         fail(FFMM_ERR_INVALID_ARG, "p2p_blocks_per_cu must lie in [0, 16]");
     if (t->m2l_rhs_block != 0 && t->m2l_rhs_block != 1 && t->m2l_rhs_block != 2 && t->m2l_rhs_block != 4)
@@ -503,19 +503,21 @@ ffmm_status ffmm_plan_autotune(ffmm_plan* p, const void* d_q, void* d_out, int32
         p->profile = false;
         FFMM_HIP(hipEventCreate(&e0));
         FFMM_HIP(hipEventCreate(&e1));
-        // time of one matvec under t: best of five after one warm-up call
+        // time of one matvec under t: after one warm-up call, three groups of three calls back to
+        // back (the steady state of repeated products, where one call's P2P and the next call's
+        // far field meet), the best group's time per call
         auto measure = [&](const ffmm_tuning& t) {
             p->tune = t;
             run_matvec(p, d_q, d_out, nrhs, FFMM_STAGE_ALL, false, false, s);
             float best_ms = 1e30f;
-            for (int rep = 0; rep < 5; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 FFMM_HIP(hipEventRecord(e0, s));
-                run_matvec(p, d_q, d_out, nrhs, FFMM_STAGE_ALL, false, false, s);
+                for (int c = 0; c < 3; ++c) run_matvec(p, d_q, d_out, nrhs, FFMM_STAGE_ALL, false, false, s);
                 FFMM_HIP(hipEventRecord(e1, s));
                 FFMM_HIP(hipEventSynchronize(e1));
                 float ms = 0.0f;
                 FFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                best_ms = std::min(best_ms, ms);
+                best_ms = std::min(best_ms, ms / 3.0f);
             }
             return best_ms;
         };
@@ -539,19 +541,41 @@ ffmm_status ffmm_plan_autotune(ffmm_plan* p, const void* d_q, void* d_out, int32
                 }
             }
         };
-        try_field(&cur.near_stream, {1, 0});
+        // the P2P placement and the M2L chunk width together (a 64-pair chunk takes the LDS a P2P
+        // block beside it would need, so the best of one depends on the other)
+        {
+            const ffmm_tuning base = cur;
+            for (int32_t ns : {1, 2, 0})
+                for (int32_t bpc : {0, 1, 2, 4})
+                    for (int32_t cw : {48, 64, 32}) {
+                        if (ns == 0 && bpc != base.p2p_blocks_per_cu) continue;
+                        if (p->prec != FFMM_FP32 && cw != base.m2l_chunk) continue;
+                        ffmm_tuning t = base;
+                        t.near_stream = ns;
+                        t.p2p_blocks_per_cu = bpc;
+                        t.m2l_chunk = cw;
+                        if (t.near_stream == cur.near_stream && t.p2p_blocks_per_cu == cur.p2p_blocks_per_cu &&
+                            t.m2l_chunk == cur.m2l_chunk)
+                            continue;
+                        const float ms = measure(t);
+                        if (ms < cur_ms) {
+                            cur_ms = ms;
+                            cur = t;
+                        }
+                    }
+        }
         try_field(&cur.m2l_by_parent, {2, 1, 0});
-        if (p->prec == FFMM_FP32 && cur.m2l_by_parent == 2) try_field(&cur.m2l_chunk, {48, 64, 32});
-        try_field(&cur.p2p_blocks_per_cu, {1, 2, 3, 4, 6, 8, 0});
         if (nrhs >= 2) try_field(&cur.m2l_rhs_block, nrhs >= 4 ? std::initializer_list<int32_t>{1, 2, 4}
                                                               : std::initializer_list<int32_t>{1, 2});
         if (p->prec == FFMM_FP32)
             for (int i = 0; i < 4; ++i) try_field(&cur.rs_slab[i], {16, 32, 64});
+        // the P2P grid once more, beside the far field as it now is
+        try_field(&cur.p2p_blocks_per_cu, {0, 1, 2, 3, 4, 6, 8});
         // confirmation: the starting configuration, the descent's choice and that choice with the
         // other P2P placement, timed in turn over three rounds; the fastest is kept (one noisy
         // time early in the descent cannot then leave a slower configuration on the plan)
         ffmm_tuning cand[3] = {start, cur, cur};
-        cand[2].near_stream = cur.near_stream ? 0 : 1;
+        cand[2].near_stream = cur.near_stream == 1 ? 2 : 1;
         float cand_ms[3] = {1e30f, 1e30f, 1e30f};
         for (int round = 0; round < 3; ++round)
             for (int c = 0; c < 3; ++c) cand_ms[c] = std::min(cand_ms[c], measure(cand[c]));

@@ -1137,7 +1137,9 @@ void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
         }
         FFMM_LAUNCH_CHECK();
     };
-    if (fork && !(stages & FFMM_STAGE_FAR)) {
+    // fork point: before the far field (near_stream 2, or P2P alone), else after the upward pass
+    const bool fork_early = fork && (!(stages & FFMM_STAGE_FAR) || p->tune.near_stream == 2);
+    if (fork_early) {
         FFMM_HIP(hipEventRecord(p->ev_fork, s));
         FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
         launch_p2p(p->near_stream);
@@ -1171,7 +1173,7 @@ void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
         }
         // P2P forks after the upward pass: beside M2L and the downward pass it costs the far field
         // less than beside M2M (measured: 3.59 against 3.68 ms per matvec at 2^20 points)
-        if (fork) {
+        if (fork && !fork_early) {
             FFMM_HIP(hipEventRecord(p->ev_fork, s));
             FFMM_HIP(hipStreamWaitEvent(p->near_stream, p->ev_fork, 0));
             launch_p2p(p->near_stream);

@@ -46,8 +46,8 @@ def test_tuning_default_and_null_plan():
     t = ff.Tuning()
     assert lib.ffmm_tuning_default(ctypes.byref(t)) == 0
     assert t.struct_size == ctypes.sizeof(ff.Tuning)
-    assert (t.near_stream, t.p2p_blocks_per_cu, t.m2l_rhs_block) == (1, 0, 0)
-    assert list(t.rs_slab) == [16, 32, 32, 16] and t.m2l_by_parent == 2 and t.m2l_chunk == 48
+    assert (t.near_stream, t.p2p_blocks_per_cu, t.m2l_rhs_block) == (2, 0, 0)
+    assert list(t.rs_slab) == [16, 32, 32, 16] and t.m2l_by_parent == 2 and t.m2l_chunk == 64
     assert lib.ffmm_tuning_default(None) == -1
     assert lib.ffmm_plan_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.ffmm_plan_get_tuning(None, ctypes.byref(t)) == -1

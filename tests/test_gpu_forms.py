@@ -129,7 +129,7 @@ def test_launch_configurations_agree_and_autotune(setup):
     base = p.matvec(q).cpu().numpy()
     # the P2P placement and stream overlap leave every operation and its order unchanged
     # and so does the chunk width of the M2L form with the transfer functions in LDS
-    for cfg in ({"near_stream": 0}, {"p2p_blocks_per_cu": 0}, {"p2p_blocks_per_cu": 1},
+    for cfg in ({"near_stream": 0}, {"near_stream": 2}, {"p2p_blocks_per_cu": 0}, {"p2p_blocks_per_cu": 1},
                 {"near_stream": 1, "p2p_blocks_per_cu": 5},
                 {"m2l_by_parent": 2, "m2l_chunk": 64, "m2l_rhs_block": 1},
                 {"m2l_by_parent": 2, "m2l_chunk": 32, "m2l_rhs_block": 2},
@@ -151,11 +151,12 @@ def test_launch_configurations_agree_and_autotune(setup):
         p.set_tuning(m2l_rhs_block=3)
     with pytest.raises(ff.FfmmError):
         p.set_tuning(m2l_chunk=40)
-    p.set_tuning(m2l_by_parent=2, m2l_chunk=48, m2l_rhs_block=0, rs_slab=[16, 32, 32, 16])
+    p.set_tuning(m2l_by_parent=2, m2l_chunk=64, m2l_rhs_block=0, rs_slab=[16, 32, 32, 16], near_stream=2,
+                 p2p_blocks_per_cu=0)
     best = p.autotune(q)
     log("autotuned: %s" % best)
     assert best == p.tuning()
-    assert best["m2l_rhs_block"] in (1, 2, 4) and best["near_stream"] in (0, 1)
+    assert best["m2l_rhs_block"] in (1, 2, 4) and best["near_stream"] in (0, 1, 2)
     assert best["m2l_by_parent"] in (0, 1, 2) and best["m2l_chunk"] in (32, 48, 64)
     got = p.matvec(q).cpu().numpy()
     assert rel_l2(got, base) < 1e-5
