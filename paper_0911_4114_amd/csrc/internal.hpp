@@ -86,6 +86,19 @@ struct LevelData {
     void* transfer = nullptr;       // [34][K] complex: T of the representative transfer vectors
     int32_t* tperm = nullptr;       // [16][K]: T_{g rep}(s_k) = T_rep(s_{tperm[g][k]})
     void* trans = nullptr;          // [8][K] complex: e^{i kappa s.(oct - 1/2) a_{l+1}} (l < L)
+    // z pairs (levels >= 3): the children of one parent with the same (x, y) position, octants o
+    // and o + 4, as one entry (zlo, zhi) with zlo the lower one present and zhi the upper one or
+    // -1, ordered by parent then by o; zstart/zcount (levels l < L) give each parent's entries
+    int64_t nz = 0;
+    int32_t* zlo = nullptr;
+    int32_t* zhi = nullptr;
+    int32_t* zpar = nullptr;        // parent of each entry (index in level l - 1)
+    int32_t* zoct = nullptr;        // octant of zlo
+    int32_t* zstart = nullptr;
+    int32_t* zcount = nullptr;
+    // (l < L) [nrows] complex: e^{i kappa cos(theta_n) a_{l+1}}, the ratio of the translations of
+    // octants o + 4 and o on row n, which does not depend on phi
+    void* zrot = nullptr;
     void* sigM = nullptr;           // [max_rhs][n][K] complex
     void* sigL = nullptr;           // [max_rhs][n][K] complex
 };
@@ -114,6 +127,12 @@ struct Resampler {
     int ntiles = 0;
     int32_t* tile_begin = nullptr;
     int32_t* tile_end = nullptr;
+    // upward pass, FP32 path: tiles of z pairs made of whole parents (at most 32 pairs each)
+    int nztiles = 0;
+    int32_t* ztile_begin = nullptr;
+    int32_t* ztile_end = nullptr;
+    int32_t* ztile_pbeg = nullptr;  // first parent of each tile
+    int32_t* ztile_pend = nullptr;  // one past its last parent
 };
 
 }  // namespace ffmm

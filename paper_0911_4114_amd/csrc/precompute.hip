@@ -641,10 +641,62 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
                 }
             }
             upload_complex<R>(p->arena, &L.trans, tr, s);
+            // octants o + 4 and o differ by a_{l+1} in z only: their translations differ by a
+            // factor that is constant on each theta row
+            std::vector<cd> zr(L.nrows);
+            for (int n = 0; n < L.nrows; ++n) {
+                const double ph = p->kappa * dirs[3 * (size_t)L.row_off[n] + 2] * ac;
+                zr[n] = cd(std::cos(ph), std::sin(ph));
+            }
+            upload_complex<R>(p->arena, &L.zrot, zr, s);
         }
     }
     p->up.assign(depth + 1, Resampler{});
     p->down.assign(depth + 1, Resampler{});
+    for (int l = 3; l <= depth; ++l) {
+        // z pairs of the children of level l - 1, and the upward tiles over them
+        LevelData& Cl = p->lev[l];
+        LevelData& Pl = p->lev[l - 1];
+        std::vector<int32_t> oct(Cl.n), cs(Pl.n), cc(Pl.n);
+        FFMM_HIP(hipMemcpy(oct.data(), Cl.octant, sizeof(int32_t) * Cl.n, hipMemcpyDeviceToHost));
+        FFMM_HIP(hipMemcpy(cs.data(), Pl.child_start, sizeof(int32_t) * Pl.n, hipMemcpyDeviceToHost));
+        FFMM_HIP(hipMemcpy(cc.data(), Pl.child_count, sizeof(int32_t) * Pl.n, hipMemcpyDeviceToHost));
+        std::vector<int> zlo, zhi, zpar, zoct, zst(Pl.n), zct(Pl.n);
+        for (int64_t pp = 0; pp < Pl.n; ++pp) {
+            int at[8];
+            std::fill(at, at + 8, -1);
+            for (int c = cs[pp]; c < cs[pp] + cc[pp]; ++c) at[oct[c]] = c;
+            zst[pp] = (int)zlo.size();
+            for (int o = 0; o < 4; ++o) {
+                if (at[o] < 0 && at[o + 4] < 0) continue;
+                zlo.push_back(at[o] >= 0 ? at[o] : at[o + 4]);
+                zhi.push_back(at[o] >= 0 ? at[o + 4] : -1);
+                zpar.push_back((int)pp);
+                zoct.push_back(at[o] >= 0 ? o : o + 4);
+            }
+            zct[pp] = (int)zlo.size() - zst[pp];
+        }
+        Cl.nz = (int64_t)zlo.size();
+        Cl.zlo = upload_int(p->arena, zlo, s);
+        Cl.zhi = upload_int(p->arena, zhi, s);
+        Cl.zpar = upload_int(p->arena, zpar, s);
+        Cl.zoct = upload_int(p->arena, zoct, s);
+        Pl.zstart = upload_int(p->arena, zst, s);
+        Pl.zcount = upload_int(p->arena, zct, s);
+        std::vector<int32_t> tb, te;
+        make_parent_tiles(std::vector<int32_t>(zct.begin(), zct.end()), tb, te);
+        std::vector<int> pb(tb.size()), pe(tb.size());
+        for (size_t t = 0; t < tb.size(); ++t) {
+            pb[t] = zpar[tb[t]];
+            pe[t] = zpar[te[t] - 1] + 1;
+        }
+        Resampler& ru = p->up[l];
+        ru.nztiles = (int)tb.size();
+        ru.ztile_begin = upload_int(p->arena, std::vector<int>(tb.begin(), tb.end()), s);
+        ru.ztile_end = upload_int(p->arena, std::vector<int>(te.begin(), te.end()), s);
+        ru.ztile_pbeg = upload_int(p->arena, pb, s);
+        ru.ztile_pend = upload_int(p->arena, pe, s);
+    }
     for (int l = 3; l <= depth; ++l) make_resampler<R>(p, p->lev[l], p->lev[l - 1], p->up[l], s);
     for (int l = 2; l < depth; ++l) make_resampler<R>(p, p->lev[l], p->lev[l + 1], p->down[l], s);
 }

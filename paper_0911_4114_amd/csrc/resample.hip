@@ -366,34 +366,50 @@ __device__ inline void mfma_mainloop(Stage& st, float* As, float* Bs, int K, f32
     }
 }
 
-// step 1 staging: A = source row data of 32 boxes (optionally parent data times conj(E_oct)),
-// B = the Dirichlet block of the row
+// step 1 staging: A = source row data of 32 boxes, or in the downward pass of 32 z pairs (lo, hi)
+// of children: the parent's data times conj(E_oct(lo)); hi's input differs from lo's by the factor
+// conj(rho(n)), constant on the source row n, so step 1 runs once per pair. B = the Dirichlet
+// block of the row.
 template <bool DOWN, int KS> struct Rs1Stage {
-    int tid, len, off, Ksrc, NA, j0;
-    int64_t c0, nb, nb_in, r;
-    const float2* sig;
-    const int32_t* parent;
-    const int32_t* octant;
-    const float2* trans;
+    int tid, len, NA, j0;
+    int64_t c0, nb;
     const float* d1;
-    static constexpr int QA = KS / 8, QB = KS / 16;
-    float2 ra[QA];
+    int off;
+    static constexpr int QA = KS / 8, QB = KS / 16, QT = DOWN ? QA : 1;
+    // source row n of this thread's tile rows (fixed over the slabs), and downward the row of
+    // the translation of lo's octant
+    const float2* gs[QA];
+    const float2* gt[QT];
+    // load() only issues the loads; store() applies conj(E) once they have landed, so that the
+    // next slab's loads stay in flight during the current slab's MFMAs
+    float2 ra[QA], rt[QT];
     float4 rb[QB];
     bool oka[QA], okb[QB];
+    __device__ void init(const float2* sig, int Ksrc, int64_t nb_in, int64_t r, const int32_t* zpar,
+                         const int32_t* zoct, const float2* trans)
+    {
+        const uint32_t rb0 = (uint32_t)(r * nb_in);
+        int bi[QA], oi[QA];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int64_t c = min(c0 + (tid + NT * q) / KS, nb - 1);
+            bi[q] = DOWN ? zpar[c] : (int)c;
+            if (DOWN) oi[q] = zoct[c];
+        }
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            gs[q] = sig + off + (uint64_t)(rb0 + (uint32_t)bi[q]) * (uint32_t)Ksrc;
+            if (DOWN) gt[q] = trans + off + (uint32_t)oi[q] * (uint32_t)Ksrc;
+        }
+    }
     __device__ void load(int k0)
     {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
             const int k = min(k0 + kk, len - 1);
-            const int64_t c = min(c0 + bc, nb - 1);
-            const int64_t cin = DOWN ? (int64_t)parent[c] : c;
-            float2 v = sig[(r * nb_in + cin) * Ksrc + off + k];
-            if (DOWN) {
-                const float2 t = trans[(int64_t)octant[c] * Ksrc + off + k];
-                v = make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
-            }
-            ra[q] = v;
+            ra[q] = gs[q][k];
+            if (DOWN) rt[q] = gt[q][k];
             oka[q] = k0 + kk < len && c0 + bc < nb;
         }
 #pragma unroll
@@ -408,24 +424,37 @@ template <bool DOWN, int KS> struct Rs1Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
-            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = oka[q] ? ra[q] : make_float2(0.f, 0.f);
+            float2 v = ra[q];
+            if (DOWN) {
+                const float2 t = rt[q];
+                v = make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
+            }
+            const bool ok = oka[q];
+            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             const int e = tid + NT * q;
-            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] = okb[q] ? rb[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 v = rb[q];
+            const bool ok = okb[q];
+            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] =
+                make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
         }
     }
 };
 
+// nt: the tile rows (boxes, or z pairs in the downward pass); nb: the boxes of the G1 layout
 template <bool DOWN, int KS>
-__global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int ntj,
+__global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows, int NA, int ntj,
                                                const int32_t* __restrict__ row_off,
                                                const int32_t* __restrict__ nphi,
                                                const float* __restrict__ d1,
                                                const float2* __restrict__ sig, int Ksrc, int64_t nb_in,
-                                               const int32_t* __restrict__ parent,
-                                               const int32_t* __restrict__ octant,
+                                               const int32_t* __restrict__ zpar,
+                                               const int32_t* __restrict__ zoct,
+                                               const int32_t* __restrict__ zlo,
+                                               const int32_t* __restrict__ zhi,
+                                               const float2* __restrict__ zrot,
                                                const float2* __restrict__ trans, float2* __restrict__ G1)
 {
     const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
@@ -437,27 +466,42 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nb, int rows, int NA, int
     st.tid = tid;
     st.len = nphi[row];
     st.off = row_off[row];
-    st.Ksrc = Ksrc;
     st.NA = NA;
     st.j0 = j0;
     st.c0 = (int64_t)blockIdx.x * (MM / 2);
-    st.nb = nb;
-    st.nb_in = nb_in;
-    st.r = blockIdx.z;
-    st.sig = sig;
-    st.parent = parent;
-    st.octant = octant;
-    st.trans = trans;
+    st.nb = nt;
     st.d1 = d1;
+    st.init(sig, Ksrc, nb_in, blockIdx.z, zpar, zoct, trans);
     f32x16 acc = {};
     mfma_mainloop<KS>(st, As, Bs, st.len, acc, wr, wc, lane);
     const int j = j0 + wc + (lane & 31);
     if (j >= NA) return;
-    const int64_t r = blockIdx.z;
+    const uint32_t rb0 = (uint32_t)(blockIdx.z * nb), bs = (uint32_t)rows * NA;   // box stride
+    float2* g = G1 + (int64_t)row * NA + j;
+    if (!DOWN) {
+#pragma unroll
+        for (int pq = 0; pq < 8; ++pq) {
+            const int64_t c = st.c0 + pair_box(wr, lane, pq);
+            if (c < nt) g[(uint64_t)(rb0 + (uint32_t)c) * bs] = make_float2(acc[2 * pq], acc[2 * pq + 1]);
+        }
+        return;
+    }
+    // lo's result as computed, hi's times conj(rho(n)); the pair indices are loaded first
+    const float2 z = zrot[row];
+    int lo[8], hi[8];
 #pragma unroll
     for (int pq = 0; pq < 8; ++pq) {
-        const int64_t c = st.c0 + pair_box(wr, lane, pq);
-        if (c < nb) G1[((r * nb + c) * rows + row) * NA + j] = make_float2(acc[2 * pq], acc[2 * pq + 1]);
+        const int64_t c = min(st.c0 + pair_box(wr, lane, pq), nt - 1);
+        lo[pq] = zlo[c];
+        hi[pq] = zhi[c];
+    }
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) {
+        if (st.c0 + pair_box(wr, lane, pq) >= nt) continue;
+        const float x = acc[2 * pq], y = acc[2 * pq + 1];
+        g[(uint64_t)(rb0 + (uint32_t)lo[pq]) * bs] = make_float2(x, y);
+        if (hi[pq] >= 0)
+            g[(uint64_t)(rb0 + (uint32_t)hi[pq]) * bs] = make_float2(x * z.x + y * z.y, y * z.x - x * z.y);
     }
 }
 
@@ -580,28 +624,64 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
 }
 
 // steps 4 + 5 staging: A = the destination row's samples on the common phi grid (row n' of the
-// half-range theta output), B = the Dirichlet block of the destination row
-template <int KS> struct Rs5Stage {
-    static constexpr int QA = KS / 8, QB = KS / 16;
-    int tid, NA, row, ntDh, len, j0;
-    int64_t cb, ce, nb, r;
-    const float2* G2;
+// half-range theta output), B = the Dirichlet block of the destination row. In the upward pass a
+// tile row is a z pair (lo, hi) of children: row(lo) + rho * row(hi), rho = e^{i kappa cos(theta_n')
+// a_child} (the translations of the two differ by this factor on row n', which step 5 does not
+// mix), so that step 5 runs once per pair and the pair's sum is translated with lo's octant.
+template <bool UP, int KS> struct Rs5Stage {
+    static constexpr int QA = KS / 8, QB = KS / 16, QH = UP ? QA : 1;
+    int tid, NA, len, j0;
+    int64_t cb, ce;
     const float* D;
-    float2 ra[QA];
+    float2 rho;
+    // row n' of this thread's tile rows (fixed over the slabs): lo and, upward, hi (lo's row when
+    // the pair has no hi)
+    const float2* glo[QA];
+    const float2* ghi[QH];
+    bool has_hi[QH];
+    // load() only issues the loads; store() forms the samples once they have landed, so that
+    // the next slab's loads stay in flight during the current slab's MFMAs
+    float4 rlo[QA], rhi[QH];   // (u', v') at the sample's column
+    bool lowh[QA];             // sample in the first half of the phi grid: u' + v', else u' - v'
     float4 rb[QB];
     bool oka[QA], okb[QB];
+    __device__ void init(const float2* G2, int64_t nb, int64_t r, int ntDh, int row, const int32_t* zlo,
+                         const int32_t* zhi)
+    {
+        const uint32_t rs = 2 * (NA / 2), bs = (uint32_t)ntDh * rs;   // row and box strides
+        const float2* g = G2 + (int64_t)row * rs;
+        const uint32_t rb0 = (uint32_t)(r * nb);
+        int lo[QA], hi[QA];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int64_t c = min(cb + (tid + NT * q) / KS, ce - 1);
+            lo[q] = UP ? zlo[c] : (int)c;
+            if (UP) hi[q] = zhi[c];
+        }
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            glo[q] = g + (uint64_t)(rb0 + (uint32_t)lo[q]) * bs;
+            if (UP) {
+                has_hi[q] = hi[q] >= 0;
+                ghi[q] = hi[q] >= 0 ? g + (uint64_t)(rb0 + (uint32_t)hi[q]) * bs : glo[q];
+            }
+        }
+    }
     __device__ void load(int k0)
     {
+        const int half = NA / 2;
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
-            const int j = min(k0 + kk, NA - 1);
-            const int64_t c = min(cb + bc, ce - 1);
-            // row n' on the common phi grid: u' + v' (j < NPhi/2), u' - v' (j >= NPhi/2)
-            const int half = NA / 2, jj = j < half ? j : j - half;
-            const float2* g = G2 + ((r * nb + c) * ntDh + row) * 2 * half + jj;
-            const float2 u = g[0], v = g[half];
-            ra[q] = j < half ? make_float2(u.x + v.x, u.y + v.y) : make_float2(u.x - v.x, u.y - v.y);
+            const int j = min(k0 + kk, NA - 1), jj = j < half ? j : j - half;
+            float2 u = glo[q][jj], v = glo[q][jj + half];
+            rlo[q] = make_float4(u.x, u.y, v.x, v.y);
+            if (UP) {
+                u = ghi[q][jj];
+                v = ghi[q][jj + half];
+                rhi[q] = make_float4(u.x, u.y, v.x, v.y);
+            }
+            lowh[q] = j < half;
             oka[q] = k0 + kk < NA && cb + bc < ce;
         }
 #pragma unroll
@@ -616,23 +696,39 @@ template <int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
-            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = oka[q] ? ra[q] : make_float2(0.f, 0.f);
+            const float sg = lowh[q] ? 1.f : -1.f;
+            const float4 a = rlo[q];
+            float x = a.x + sg * a.z, y = a.y + sg * a.w;
+            if (UP && has_hi[q]) {
+                const float4 h = rhi[q];
+                const float hx = h.x + sg * h.z, hy = h.y + sg * h.w;
+                x += rho.x * hx - rho.y * hy;
+                y += rho.x * hy + rho.y * hx;
+            }
+            const bool ok = oka[q];
+            *(float2*)&As[(e % KS) * MAP + 2 * (e / KS)] = make_float2(ok ? x : 0.f, ok ? y : 0.f);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             const int e = tid + NT * q;
-            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] = okb[q] ? rb[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 v = rb[q];
+            const bool ok = okb[q];
+            *(float4*)&Bs[(e >> 4) * MBP + 4 * (e & 15)] =
+                make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
         }
     }
 };
 
+// UP: tiles of whole parents' z pairs (tile_begin/tile_end over the pairs, zstart/zcount each
+// parent's pairs); DOWN: tiles of 32 consecutive child boxes.
 template <bool UP, int KS>
 __global__ __launch_bounds__(NT) void rs5_mfma(
     int64_t nb, int NA, int ntD, int ntj, const int32_t* __restrict__ row_off,
     const int32_t* __restrict__ nphi, const float* __restrict__ d5, const float2* __restrict__ G2, int Kd,
     const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
-    const int32_t* __restrict__ parent, const int32_t* __restrict__ octant,
-    const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_count,
+    const int32_t* __restrict__ tile_pbeg, const int32_t* __restrict__ tile_pend,
+    const int32_t* __restrict__ zlo, const int32_t* __restrict__ zhi, const int32_t* __restrict__ zoct,
+    const float2* __restrict__ zrot, const int32_t* __restrict__ zstart, const int32_t* __restrict__ zcount,
     const float2* __restrict__ trans, int64_t nb_out, float2* __restrict__ out)
 {
     const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
@@ -649,66 +745,72 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     }
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    // the A slab also holds the translated children (32 x 64 complex) in the upward pass
+    // the A slab also holds the translated pairs (32 x 64 complex) in the upward pass
     constexpr int kA = (UP && KS * MAP < 2 * (MM / 2) * MN) ? 2 * (MM / 2) * MN : KS * MAP;
     __shared__ __align__(16) float As[kA];
     __shared__ __align__(16) float Bs[KS * MBP];
-    Rs5Stage<KS> st;
+    Rs5Stage<UP, KS> st;
     st.tid = tid;
     st.NA = NA;
-    st.row = row;
-    st.ntDh = ntD / 2 + 1;
     st.len = len;
     st.j0 = j0;
     st.cb = cb;
     st.ce = ce;
-    st.nb = nb;
-    st.r = r;
-    st.G2 = G2;
     st.D = d5 + (int64_t)off * NA;
+    st.rho = UP ? zrot[row] : make_float2(1.f, 0.f);
+    st.init(G2, nb, r, ntD / 2 + 1, row, zlo, zhi);
     f32x16 acc = {};
     mfma_mainloop<KS>(st, As, Bs, NA, acc, wr, wc, lane);
     const int colw = wc + (lane & 31);
     const int jp = j0 + colw;
     if (!UP) {
+        // add to I: the eight reads are issued before any write
         if (jp >= len) return;
+        float2* o = out + off + jp;
+        const uint32_t rb0 = (uint32_t)(r * nb_out);
+        float2 cur[8];
+#pragma unroll
+        for (int pq = 0; pq < 8; ++pq)
+            cur[pq] = o[(uint64_t)(rb0 + (uint32_t)min(cb + pair_box(wr, lane, pq), ce - 1)) * (uint32_t)Kd];
 #pragma unroll
         for (int pq = 0; pq < 8; ++pq) {
             const int64_t c = cb + pair_box(wr, lane, pq);
-            if (c >= ce) continue;
-            float2& o = out[(r * nb_out + c) * Kd + off + jp];
-            o.x += acc[2 * pq];
-            o.y += acc[2 * pq + 1];
+            if (c < ce)
+                o[(uint64_t)(rb0 + (uint32_t)c) * (uint32_t)Kd] =
+                    make_float2(cur[pq].x + acc[2 * pq], cur[pq].y + acc[2 * pq + 1]);
         }
         return;
     }
-    // UP: translate each child on the parent grid, then sum the children of every parent (the
-    // slabs are free after the main loop's last barrier)
+    // UP: translate each pair on the parent grid (lo's octant), then sum the pairs of every parent
+    // (the slabs are free after the main loop's last barrier). The octant and translation loads
+    // of all eight results are issued before any is used.
     float2* S = (float2*)As;   // 32 x 64 complex
+    int oc[8];
+    float2 tv[8];
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) oc[pq] = zoct[min(cb + pair_box(wr, lane, pq), ce - 1)];
+    const float2* tr = trans + off + min(jp, len - 1);
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) tv[pq] = tr[(int64_t)oc[pq] * Kd];
 #pragma unroll
     for (int pq = 0; pq < 8; ++pq) {
         const int bx = pair_box(wr, lane, pq);
-        const int64_t c = cb + bx;
-        float2 v = make_float2(0.f, 0.f);
-        if (jp < len && c < ce) {
-            const float2 t = trans[(int64_t)octant[c] * Kd + off + jp];
-            const float x = acc[2 * pq], y = acc[2 * pq + 1];
-            v = make_float2(x * t.x - y * t.y, x * t.y + y * t.x);
-        }
-        S[bx * MN + colw] = v;
+        const bool ok = jp < len && cb + bx < ce;
+        const float2 t = tv[pq];
+        const float x = acc[2 * pq], y = acc[2 * pq + 1];
+        S[bx * MN + colw] = make_float2(ok ? x * t.x - y * t.y : 0.f, ok ? x * t.y + y * t.x : 0.f);
     }
     __syncthreads();
-    const int64_t p0 = parent[cb], p1 = parent[ce - 1];
-    const int npar = (int)(p1 - p0 + 1);
+    const int p0 = tile_pbeg[blockIdx.x], npar = tile_pend[blockIdx.x] - p0;
     for (int e = tid; e < MN * npar; e += NT) {
         const int i = e % MN, pi = e / MN;
         const int jj = j0 + i;
         if (jj >= len) continue;
-        const int64_t pp = p0 + pi;
-        const int64_t a = child_start[pp], cnt = child_count[pp];
+        const int pp = p0 + pi;
+        const int a = zstart[pp] - (int)cb, cnt = zcount[pp];
         float2 sum = make_float2(0.f, 0.f);
-        for (int64_t c = a; c < a + cnt; ++c) {
-            const float2 v = S[(int)(c - cb) * MN + i];
+        for (int c = a; c < a + cnt; ++c) {
+            const float2 v = S[c * MN + i];
             sum.x += v.x;
             sum.y += v.y;
         }
@@ -832,22 +934,27 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     const int64_t nb = Cl.n;
     {
         const int ntj = cdiv(NA, MN);
-        dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_src, nrhs);
-        if (up)
+        if (up) {
+            dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_src, nrhs);
             with_ks(p->tune.rs_slab[0], [&](auto t) {
-                hipLaunchKernelGGL((rs1_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
+                hipLaunchKernelGGL((rs1_mfma<false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
                                    (const float*)rs.d1, (const float2*)S.sigM, S.K, S.n,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr,
-                                   (const float2*)nullptr, G1);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const float2*)nullptr, (const float2*)nullptr, G1);
             });
-        else
+        } else {
+            // one contraction per z pair of children
+            dim3 grid(cdiv(Cl.nz, MM / 2), ntj * rs.rows_src, nrhs);
             with_ks(p->tune.rs_slab[0], [&](auto t) {
-                hipLaunchKernelGGL((rs1_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb,
+                hipLaunchKernelGGL((rs1_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi,
-                                   (const float*)rs.d1, (const float2*)S.sigL, S.K, S.n, Cl.parent,
-                                   Cl.octant, (const float2*)S.trans, G1);
+                                   (const float*)rs.d1, (const float2*)S.sigL, S.K, S.n, Cl.zpar,
+                                   Cl.zoct, Cl.zlo, Cl.zhi, (const float2*)S.zrot,
+                                   (const float2*)S.trans, G1);
             });
+        }
         FFMM_LAUNCH_CHECK();
     }
     {
@@ -864,13 +971,14 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         for (int v : D.par.nphi) mx = std::max(mx, v);
         const int ntj = cdiv(mx, MN);
         if (up) {
-            dim3 grid((unsigned)rs.ntiles, ntj * rs.rows_dst, nrhs);
+            // tiles of whole parents' z pairs
+            dim3 grid((unsigned)rs.nztiles, ntj * rs.rows_dst, nrhs);
             with_ks(p->tune.rs_slab[2], [&](auto t) {
                 hipLaunchKernelGGL((rs5_mfma<true, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
                                    rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const float*)rs.d5,
-                                   (const float2*)G2, D.K, rs.tile_begin, rs.tile_end, Cl.parent,
-                                   Cl.octant, D.child_start, D.child_count, (const float2*)D.trans, D.n,
-                                   (float2*)D.sigM);
+                                   (const float2*)G2, D.K, rs.ztile_begin, rs.ztile_end, rs.ztile_pbeg,
+                                   rs.ztile_pend, Cl.zlo, Cl.zhi, Cl.zoct, (const float2*)D.zrot,
+                                   D.zstart, D.zcount, (const float2*)D.trans, D.n, (float2*)D.sigM);
             });
         } else {
             dim3 grid(cdiv(nb, MM / 2), ntj * rs.rows_dst, nrhs);
@@ -880,7 +988,9 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
                                    (const float2*)G2, D.K, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr,
-                                   (const int32_t*)nullptr, (const float2*)nullptr, D.n, (float2*)D.sigL);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const float2*)nullptr,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const float2*)nullptr,
+                                   D.n, (float2*)D.sigL);
             });
         }
         FFMM_LAUNCH_CHECK();
