@@ -745,10 +745,13 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     }
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    // the A slab also holds the translated pairs (32 x 64 complex) in the upward pass
-    constexpr int kA = (UP && KS * MAP < 2 * (MM / 2) * MN) ? 2 * (MM / 2) * MN : KS * MAP;
-    __shared__ __align__(16) float As[kA];
-    __shared__ __align__(16) float Bs[KS * MBP];
+    // one LDS array: the A and B slabs during the contraction, then (upward) the translated
+    // pairs (32 x 64 complex) for the sums over each parent's pairs
+    constexpr int kL = (UP && KS * (MAP + MBP) < 2 * (MM / 2) * MN) ? 2 * (MM / 2) * MN : KS * (MAP + MBP);
+    __shared__ __align__(16) float Ls[kL];
+    __shared__ int pz[2][MM / 2];   // upward: zstart - cb and zcount of the tile's parents
+    float* As = Ls;
+    float* Bs = Ls + KS * MAP;
     Rs5Stage<UP, KS> st;
     st.tid = tid;
     st.NA = NA;
@@ -759,62 +762,72 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     st.D = d5 + (int64_t)off * NA;
     st.rho = UP ? zrot[row] : make_float2(1.f, 0.f);
     st.init(G2, nb, r, ntD / 2 + 1, row, zlo, zhi);
-    f32x16 acc = {};
-    mfma_mainloop<KS>(st, As, Bs, NA, acc, wr, wc, lane);
     const int colw = wc + (lane & 31);
     const int jp = j0 + colw;
+    const int jpc = min(jp, len - 1);
+    // upward: the pair ranges of the tile's parents, staged in LDS before the contraction
+    int p0 = 0, npar = 0;
+    const uint32_t rbo = (uint32_t)(r * nb_out);
+    if (UP) {
+        p0 = tile_pbeg[blockIdx.x];
+        npar = tile_pend[blockIdx.x] - p0;
+        if (tid < npar) {
+            pz[0][tid] = zstart[p0 + tid] - (int)cb;
+            pz[1][tid] = zcount[p0 + tid];
+        }
+    }
+    f32x16 acc = {};
+    mfma_mainloop<KS>(st, As, Bs, NA, acc, wr, wc, lane);
+    float2 ev[8];
     if (!UP) {
         // add to I: the eight reads are issued before any write
         if (jp >= len) return;
         float2* o = out + off + jp;
-        const uint32_t rb0 = (uint32_t)(r * nb_out);
-        float2 cur[8];
 #pragma unroll
         for (int pq = 0; pq < 8; ++pq)
-            cur[pq] = o[(uint64_t)(rb0 + (uint32_t)min(cb + pair_box(wr, lane, pq), ce - 1)) * (uint32_t)Kd];
+            ev[pq] = o[(uint64_t)(rbo + (uint32_t)min(cb + pair_box(wr, lane, pq), ce - 1)) * (uint32_t)Kd];
 #pragma unroll
         for (int pq = 0; pq < 8; ++pq) {
             const int64_t c = cb + pair_box(wr, lane, pq);
             if (c < ce)
-                o[(uint64_t)(rb0 + (uint32_t)c) * (uint32_t)Kd] =
-                    make_float2(cur[pq].x + acc[2 * pq], cur[pq].y + acc[2 * pq + 1]);
+                o[(uint64_t)(rbo + (uint32_t)c) * (uint32_t)Kd] =
+                    make_float2(ev[pq].x + acc[2 * pq], ev[pq].y + acc[2 * pq + 1]);
         }
         return;
     }
-    // UP: translate each pair on the parent grid (lo's octant), then sum the pairs of every parent
-    // (the slabs are free after the main loop's last barrier). The octant and translation loads
-    // of all eight results are issued before any is used.
-    float2* S = (float2*)As;   // 32 x 64 complex
-    int oc[8];
-    float2 tv[8];
+    {
+        // the octant of each result's pair, then its translation: all loads issued before use
+        int oc[8];
 #pragma unroll
-    for (int pq = 0; pq < 8; ++pq) oc[pq] = zoct[min(cb + pair_box(wr, lane, pq), ce - 1)];
-    const float2* tr = trans + off + min(jp, len - 1);
+        for (int pq = 0; pq < 8; ++pq) oc[pq] = zoct[min(cb + pair_box(wr, lane, pq), ce - 1)];
+        const float2* tr = trans + off + jpc;
 #pragma unroll
-    for (int pq = 0; pq < 8; ++pq) tv[pq] = tr[(int64_t)oc[pq] * Kd];
+        for (int pq = 0; pq < 8; ++pq) ev[pq] = tr[(uint32_t)oc[pq] * (uint32_t)Kd];
+    }
+    // UP: translate each pair on the parent grid, then sum the pairs of every parent (the slabs
+    // are free after the main loop's last barrier)
+    float2* S = (float2*)Ls;   // 32 x 64 complex
 #pragma unroll
     for (int pq = 0; pq < 8; ++pq) {
         const int bx = pair_box(wr, lane, pq);
         const bool ok = jp < len && cb + bx < ce;
-        const float2 t = tv[pq];
+        const float2 t = ev[pq];
         const float x = acc[2 * pq], y = acc[2 * pq + 1];
         S[bx * MN + colw] = make_float2(ok ? x * t.x - y * t.y : 0.f, ok ? x * t.y + y * t.x : 0.f);
     }
     __syncthreads();
-    const int p0 = tile_pbeg[blockIdx.x], npar = tile_pend[blockIdx.x] - p0;
     for (int e = tid; e < MN * npar; e += NT) {
         const int i = e % MN, pi = e / MN;
         const int jj = j0 + i;
         if (jj >= len) continue;
-        const int pp = p0 + pi;
-        const int a = zstart[pp] - (int)cb, cnt = zcount[pp];
+        const int a = pz[0][pi], cnt = pz[1][pi];
         float2 sum = make_float2(0.f, 0.f);
         for (int c = a; c < a + cnt; ++c) {
             const float2 v = S[c * MN + i];
             sum.x += v.x;
             sum.y += v.y;
         }
-        out[(r * nb_out + pp) * Kd + off + jj] = sum;
+        out[(uint64_t)(rbo + (uint32_t)(p0 + pi)) * (uint32_t)Kd + off + jj] = sum;
     }
 }
 
