@@ -269,8 +269,9 @@ typedef struct {
     int32_t m2l_rhs_block;      /* right-hand sides sharing each transfer-function read in M2L:
                                    1, 2 or 4 (at most 2 with m2l_by_parent); 0 (default) = the
                                    largest that does not exceed nrhs */
-    int32_t rs_slab[4];         /* FP32 resample k-slab depth (16, 32 or 64) of step 1, steps 2+3,
-                                   upward steps 4+5 and downward steps 4+5; default 16, 32, 32, 16 */
+    int32_t rs_slab[4];         /* resample k-slab depth (16, 32 or 64; FP64 plans take 32 for 64)
+                                   of step 1, steps 2+3, upward steps 4+5 and downward steps 4+5;
+                                   default 16, 32, 32, 16 */
     int32_t m2l_by_parent;      /* M2L form. 2 (default): by parent pairs, with the transfer
                                    functions of a chunk of m2l_chunk directions gathered into LDS
                                    once per block and reused for a range of parents (FP32 plans;

@@ -110,9 +110,7 @@ struct Resampler {
     int rows_src = 0, rows_dst = 0;
     int K_src = 0, K_dst = 0;
     void* d1 = nullptr;             // step 1, per source row n: [N_phi,n][nphi_all] (j fastest)
-    void* dth = nullptr;            // step 3: [nt_src][nt_dth] (t' fastest, zero-padded)
-    int nt_dth = 0;                 // row stride of dth: nt_dst rounded up to a multiple of 4
-    // the theta step on half ranges (eqn. FourierSphereSym), FP32 path: operators for the even
+    // the theta step on half ranges (eqn. FourierSphereSym): operators for the even
     // and the odd parts of the phi columns, rows 0..N_theta/2 -> 0..N'_theta/2, each
     // [nt_src/2+1][ldh] (zero-padded), the even one first, the factor 1/2 of the split folded in
     void* dth_h = nullptr;
@@ -123,11 +121,7 @@ struct Resampler {
     int32_t* d_dst_row_off = nullptr;
     int32_t* d_dst_nphi = nullptr;
     int32_t* d_dst_row_of_k = nullptr; // [K_dst] row of each destination sample
-    // upward pass: child tiles made of whole parents (at most 32 children each)
-    int ntiles = 0;
-    int32_t* tile_begin = nullptr;
-    int32_t* tile_end = nullptr;
-    // upward pass, FP32 path: tiles of z pairs made of whole parents (at most 32 pairs each)
+    // upward pass: tiles of z pairs made of whole parents (at most 32 pairs each)
     int nztiles = 0;
     int32_t* ztile_begin = nullptr;
     int32_t* ztile_end = nullptr;

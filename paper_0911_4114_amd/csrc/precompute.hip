@@ -472,8 +472,8 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     rs.rows_dst = D.nrows;
     rs.K_src = S.K;
     rs.K_dst = D.K;
-    rs.nt_dth = (rs.nt_dst + 3) / 4 * 4;
-    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * rs.nt_dth, 0.0), d5((size_t)D.K * na);
+    const int ldt = rs.nt_dst;   // row stride of the full-range theta operator (host only)
+    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * ldt, 0.0), d5((size_t)D.K * na);
     for (int n = 0; n < S.nrows; ++n) {
         const int len = S.par.nphi[n];
         double* blk = &d1[(size_t)S.row_off[n] * na];
@@ -482,7 +482,7 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     }
     for (int t = 0; t < rs.nt_src; ++t)
         for (int tp = 0; tp < rs.nt_dst; ++tp)
-            dth[(size_t)t * rs.nt_dth + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
+            dth[(size_t)t * ldt + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
     for (int n = 0; n < D.nrows; ++n) {
         const int len = D.par.nphi[n];
         double* blk = &d5[(size_t)D.row_off[n] * na];
@@ -490,7 +490,6 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
             for (int jp = 0; jp < len; ++jp) blk[(size_t)j * len + jp] = dirichlet(na, len, j, jp);
     }
     upload_real<R>(p->arena, &rs.d1, d1, s);
-    upload_real<R>(p->arena, &rs.dth, dth, s);
     {
         // half-range theta operators: an even (odd) circle sequence x, x(N - t) = +-x(t), is
         // resampled by sum over the half range of x(t) (D[t][t'] +- D[N - t][t']), the rows t = 0,
@@ -502,9 +501,9 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
         double* dodd = dh.data() + (size_t)nsh * rs.ldh;
         for (int t = 0; t < nsh; ++t)
             for (int tp = 0; tp < ndh; ++tp) {
-                const double a = dth[(size_t)t * rs.nt_dth + tp];
+                const double a = dth[(size_t)t * ldt + tp];
                 const bool edge = (t == 0 || 2 * t == ns);
-                const double b = edge ? 0.0 : dth[(size_t)(ns - t) * rs.nt_dth + tp];
+                const double b = edge ? 0.0 : dth[(size_t)(ns - t) * ldt + tp];
                 de[(size_t)t * rs.ldh + tp] = 0.5 * (a + b);
                 dodd[(size_t)t * rs.ldh + tp] = edge ? 0.0 : 0.5 * (a - b);
             }
@@ -519,14 +518,6 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     for (int n = 0; n < D.nrows; ++n)
         for (int k = D.row_off[n]; k < D.row_off[n + 1]; ++k) rok[k] = n;
     rs.d_dst_row_of_k = upload_int(p->arena, rok, s);
-    if (D.l == S.l - 1) {
-        std::vector<int32_t> cc(D.n), tb, te;
-        FFMM_HIP(hipMemcpy(cc.data(), D.child_count, sizeof(int32_t) * D.n, hipMemcpyDeviceToHost));
-        make_parent_tiles(cc, tb, te);
-        rs.ntiles = (int)tb.size();
-        rs.tile_begin = upload_int(p->arena, std::vector<int>(tb.begin(), tb.end()), s);
-        rs.tile_end = upload_int(p->arena, std::vector<int>(te.begin(), te.end()), s);
-    }
 }
 
 template <class R>
