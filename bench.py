@@ -543,8 +543,15 @@ def main():
         ms64 = timed(lambda: p64.matvec(q64), max(3, args.steps // 2), 2)
         out64 = p64.matvec(q64).cpu().numpy()
         i64 = p64.info()
+        # per-stage times of the FP64 plan (every stage alone, as for FP32)
+        p64.profile(True)
+        for _ in range(3):
+            p64.matvec(q64)
+        prof64 = p64.profile_read()
+        p64.profile(False)
         fp64 = {"value": n / (ms64 * 1e-3) / 1e6, "ms_per_step": ms64, "setup_s": s64,
-                "depth": i64["depth"], "eps": 1e-6}
+                "depth": i64["depth"], "eps": 1e-6,
+                "stages_ms": {k: round(v[0] / 3, 4) for k, v in prof64.items()}}
         if not args.no_cpu:
             fp64["rel_err"] = float(np.linalg.norm(out64[tg] - ref) / np.linalg.norm(ref))
         log("fp64 %.3f ms err %s" % (ms64, fp64.get("rel_err")))
