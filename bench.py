@@ -362,8 +362,16 @@ def main():
         tuned = pb.autotune(qb)
         tune_b_s = time.perf_counter() - t0
         msb = timed(lambda: pb.matvec(qb), max(3, args.steps // 2), 1)
+        # per-stage times of the batched matvec (every stage alone, P2P on the whole GPU)
+        pb.set_tuning(p2p_blocks_per_cu=0)
+        pb.profile(True)
+        pb.matvec(qb)
+        profb = pb.profile_read()
+        pb.profile(False)
+        pb.set_tuning(**tuned)
         batched = {"nrhs": nb_rhs, "value": n * nb_rhs / (msb * 1e-3) / 1e6, "ms_per_step": msb,
-                   "tuning": tuned, "autotune_s": tune_b_s}
+                   "tuning": tuned, "autotune_s": tune_b_s,
+                   "stages_ms": {k: round(v[0], 4) for k, v in profb.items()}}
         if not args.no_cpu:
             ob = pb.matvec(qb)[3].cpu().numpy().astype(np.complex128)
             qh = wl.plane_wave_charges(x, args.kappa, nb_rhs, seed=2)[3]
