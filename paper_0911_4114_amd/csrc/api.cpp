@@ -142,14 +142,12 @@ static void allocate_workspaces(ffmm_plan* p)
         const Resampler& rs = p->up[l];
         const int64_t nb = p->lev[l].n;
         s1 = std::max(s1, (size_t)nb * rs.rows_src * rs.nphi_all);
-        s2 = std::max(s2, (size_t)nb * (rs.nphi_all / 2) * rs.nt_dst);
-        s2 = std::max(s2, (size_t)nb * rs.nphi_all * (rs.nt_dst / 2 + 1));   // half-range layout
+        s2 = std::max(s2, (size_t)nb * rs.nphi_all * (rs.nt_dst / 2 + 1));   // theta rows 0..N'/2
     }
     for (int l = 2; l < p->depth; ++l) {
         const Resampler& rs = p->down[l];
         const int64_t nb = p->lev[l + 1].n;
         s1 = std::max(s1, (size_t)nb * rs.rows_src * rs.nphi_all);
-        s2 = std::max(s2, (size_t)nb * (rs.nphi_all / 2) * rs.nt_dst);
         s2 = std::max(s2, (size_t)nb * rs.nphi_all * (rs.nt_dst / 2 + 1));
     }
     p->scratch1_bytes = cs * s1 * mr;

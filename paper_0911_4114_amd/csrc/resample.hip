@@ -307,10 +307,11 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 // 0..N_theta/2 split into u = F_m + F_{m + NPhi/2} (even phi modes, even in theta) and
 // v = F_m - F_{m + NPhi/2} (odd modes, odd in theta); the theta step is then two half-range
 // contractions u' = De^T u, v' = Do^T v (De, Do carry the factor 1/2) onto the destination rows
-// 0..N'_theta/2, where F'_m = u' + v', F'_{m + NPhi/2} = u' - v' (formed by steps 4 + 5). Half the
-// work of resampling the full theta circle. A block tile stacks 32 rows t' of De (the waves on
-// tile rows 0..31, which read u) over the same 32 rows of Do (tile rows 32..63, which read v).
-// G2: [rhs][box][N'_theta/2 + 1][2][NPhi/2] complex: u' then v' of each row.
+// 0..N'_theta/2, where F'_m = u' + v', F'_{m + NPhi/2} = u' - v'. Half the work of resampling the
+// full theta circle. A block tile stacks 32 rows t' of De (the waves on tile rows 0..31, which
+// read u) over the same 32 rows of Do (tile rows 32..63, which read v); the two halves meet in
+// LDS after the contraction, and the u' waves write F'_m, the v' waves F'_{m + NPhi/2}.
+// G2: [rhs][box][N'_theta/2 + 1][NPhi] complex, each row on the common phi grid.
 // dh holds De then Do, each [N_theta/2 + 1][ldh].
 template <class R, int KS>
 __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, int ntSh, int ntDh, int ldh,
@@ -321,8 +322,12 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     using C = typename cpx<R>::type;
     using T = MT<R>;
     constexpr int QA = KS / 16, QB = KS / 8;
-    __shared__ __align__(16) R As[KS * MAP];
-    __shared__ __align__(16) R Bs[2 * KS * MBP];
+    // the A slab and the u, v halves of the B slab; after the contraction, the 64 x 64 tile of
+    // results (u' rows over v' rows)
+    constexpr int kL = KS * MAP + 2 * KS * MBP > MM * MN ? KS * MAP + 2 * KS * MBP : MM * MN;
+    __shared__ __align__(16) R Ls[kL];
+    R* As = Ls;
+    R* Bs = Ls + KS * MAP;
     const int half = NA / 2;
     const int i0 = blockIdx.y * (MM / 2);
     const int64_t r = blockIdx.z;
@@ -402,11 +407,17 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
         }
         __syncthreads();
     }
-    // value q: destination row i0 + vrow, tile column wc + vcol = (box, phi_m, re/im)
+    // value q: destination row i0 + vrow, tile column wc + vcol = (box, phi_m, re/im); the u'
+    // waves (even) and v' waves (odd) exchange their values through LDS (the slabs are free after
+    // the main loop's last barrier), then form F'_m = u' + v' and F'_{m + NPhi/2} = u' - v'
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Ls[(wr + T::vrow(lane, q)) * MN + wc + T::vcol(lane, q)] = T::val(acc, q);
+    __syncthreads();
+    const R sg = odd ? R(-1) : R(1);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int col = wc + T::vcol(lane, q), cc = col >> 1, part = col & 1;
-        const int tp = i0 + T::vrow(lane, q);
+        const int tr = T::vrow(lane, q), tp = i0 + tr;
         if (g0 + cc >= ncols || tp >= ntDh) continue;
         int m = m0 + cc;
         int64_t c = cbase;
@@ -414,14 +425,15 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
             m -= half;
             ++c;
         }
-        R* base = (R*)(G2 + ((r * nb + c) * ntDh * 2 + (odd ? 1 : 0)) * half + m) + part;
-        base[(int64_t)tp * 2 * half * 2] = T::val(acc, q);
+        const R u = Ls[tr * MN + col], v = Ls[(32 + tr) * MN + col];
+        R* base = (R*)(G2 + ((r * nb + c) * ntDh + tp) * NA + m + (odd ? half : 0)) + part;
+        *base = u + sg * v;
     }
 }
 
-// steps 4 + 5 staging: A = the destination row's samples on the common phi grid (row n' of the
-// half-range theta output), B = the Dirichlet block of the destination row. In the upward pass a
-// tile row is a z pair (lo, hi) of children: row(lo) + rho row(hi).
+// steps 4 + 5 staging: A = the destination row n' of G2 (on the common phi grid), B = the
+// Dirichlet block of the destination row. In the upward pass a tile row is a z pair (lo, hi) of
+// children: row(lo) + rho row(hi).
 template <class R, bool UP, int KS> struct Rs5Stage {
     using C = typename cpx<R>::type;
     static constexpr int QA = KS / 8, QB = KS / 16, QH = UP ? QA : 1;
@@ -434,17 +446,16 @@ template <class R, bool UP, int KS> struct Rs5Stage {
     const C* glo[QA];
     const C* ghi[QH];
     bool has_hi[QH];
-    // load() only issues the loads; store() forms the samples once they have landed, so that
+    // load() only issues the loads; store() forms the pair sums once they have landed, so that
     // the next slab's loads stay in flight during the current slab's MFMAs
-    C rlu[QA], rlv[QA], rhu[QH], rhv[QH];   // (u', v') at the sample's column
-    bool lowh[QA];                          // sample in the first half: u' + v', else u' - v'
+    C rl[QA], rh[QH];
     V4<R> rb[QB];
     bool oka[QA], okb[QB];
     __device__ void init(const C* G2, int64_t nb, int64_t r, int ntDh, int row, const int32_t* zlo,
                          const int32_t* zhi)
     {
-        const uint32_t rs = 2 * (NA / 2), bs = (uint32_t)ntDh * rs;   // row and box strides
-        const C* g = G2 + (int64_t)row * rs;
+        const uint32_t bs = (uint32_t)ntDh * NA;   // box stride
+        const C* g = G2 + (int64_t)row * NA;
         const uint32_t rb0 = (uint32_t)(r * nb);
         int lo[QA], hi[QA];
 #pragma unroll
@@ -464,18 +475,12 @@ template <class R, bool UP, int KS> struct Rs5Stage {
     }
     __device__ void load(int k0)
     {
-        const int half = NA / 2;
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
-            const int j = min(k0 + kk, NA - 1), jj = j < half ? j : j - half;
-            rlu[q] = glo[q][jj];
-            rlv[q] = glo[q][jj + half];
-            if (UP) {
-                rhu[q] = ghi[q][jj];
-                rhv[q] = ghi[q][jj + half];
-            }
-            lowh[q] = j < half;
+            const int j = min(k0 + kk, NA - 1);
+            rl[q] = glo[q][j];
+            if (UP) rh[q] = ghi[q][j];
             oka[q] = k0 + kk < NA && cb + bc < ce;
         }
 #pragma unroll
@@ -490,12 +495,11 @@ template <class R, bool UP, int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
-            const R sg = lowh[q] ? R(1) : R(-1);
-            R x = rlu[q].x + sg * rlv[q].x, y = rlu[q].y + sg * rlv[q].y;
+            R x = rl[q].x, y = rl[q].y;
             if (UP && has_hi[q]) {
-                const R hx = rhu[q].x + sg * rhv[q].x, hy = rhu[q].y + sg * rhv[q].y;
-                x += rho.x * hx - rho.y * hy;
-                y += rho.x * hy + rho.y * hx;
+                const C h = rh[q];
+                x += rho.x * h.x - rho.y * h.y;
+                y += rho.x * h.y + rho.y * h.x;
             }
             const bool ok = oka[q];
             *(C*)&As[(e % KS) * MAP + 2 * (e / KS)] = cx<R>(ok ? x : R(0), ok ? y : R(0));
