@@ -548,6 +548,13 @@ def main():
         p64 = ff.Plan(xt, args.kappa, 1e-6, precision="fp64")
         torch.cuda.synchronize()
         s64 = time.perf_counter() - t0
+        tune64_s = None
+        if not args.no_tune and not args.serial:
+            # the FP64 plan's own launch configuration (setup, not timed)
+            t0 = time.perf_counter()
+            p64.autotune(q64)
+            torch.cuda.synchronize()
+            tune64_s = time.perf_counter() - t0
         ms64 = timed(lambda: p64.matvec(q64), max(3, args.steps // 2), 2)
         out64 = p64.matvec(q64).cpu().numpy()
         i64 = p64.info()
@@ -558,7 +565,7 @@ def main():
         prof64 = p64.profile_read()
         p64.profile(False)
         fp64 = {"value": n / (ms64 * 1e-3) / 1e6, "ms_per_step": ms64, "setup_s": s64,
-                "depth": i64["depth"], "eps": 1e-6,
+                "depth": i64["depth"], "eps": 1e-6, "tuning": p64.tuning(), "autotune_s": tune64_s,
                 "stages_ms": {k: round(v[0] / 3, 4) for k, v in prof64.items()}}
         if not args.no_cpu:
             fp64["rel_err"] = float(np.linalg.norm(out64[tg] - ref) / np.linalg.norm(ref))

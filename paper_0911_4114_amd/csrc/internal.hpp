@@ -55,6 +55,17 @@ struct DeviceArena {
 };
 
 // One level of the octree with its quadrature and tables.
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2. This bijection of
+// [0, nblocks) gives every XCD a contiguous range of logical blocks, so blocks that read the same
+// data (Morton-adjacent boxes, or the tiles of one column range) are served by one L2.
+__device__ inline unsigned xcd_block(unsigned b, unsigned nblocks)
+{
+    constexpr unsigned kXcd = 8;
+    const unsigned per = nblocks / kXcd, rem = nblocks % kXcd;
+    const unsigned x = b % kXcd, i = b / kXcd;
+    return x * per + min(x, rem) + i;
+}
+
 struct LevelData {
     int l = 0;
     int64_t n = 0;            // occupied boxes

@@ -68,17 +68,6 @@ template <class R> __device__ inline void two_sum(R a, R b, R& s, R& e)
 
 template <class R> __device__ inline R shfl_down(R v, int d) { return __shfl_down(v, d, kWave); }
 
-// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2. This bijection of
-// [0, nblocks) gives every XCD a contiguous range of logical blocks, so Morton-adjacent boxes
-// (which share interaction-list sources and neighbours) are served by one L2.
-__device__ inline unsigned xcd_block(unsigned b, unsigned nblocks)
-{
-    constexpr unsigned kXcd = 8;
-    const unsigned per = nblocks / kXcd, rem = nblocks % kXcd;
-    const unsigned x = b % kXcd, i = b / kXcd;
-    return x * per + min(x, rem) + i;
-}
-
 // Kernels that give each wave its own box run kWpb waves per block: blocks of one wave are few
 // per CU and leave the SIMDs short of waves to hide latency with. The waves of a block then work
 // on different boxes and hand LDS data between their own lanes only: a wave executes its LDS

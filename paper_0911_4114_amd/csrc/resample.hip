@@ -313,9 +313,13 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 // LDS after the contraction, and the u' waves write F'_m, the v' waves F'_{m + NPhi/2}.
 // G2: [rhs][box][N'_theta/2 + 1][NPhi] complex, each row on the common phi grid.
 // dh holds De then Do, each [N_theta/2 + 1][ldh].
+// Grid: one dimension of column tiles x row tiles (ny of them). With several row tiles the row
+// tiles of a column tile are consecutive logical blocks of one XCD, so that the tile's G1 columns,
+// read by every row tile, come from that XCD's L2 after the first (with one row tile the plain
+// order measured faster).
 template <class R, int KS>
 __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, int ntSh, int ntDh, int ldh,
-                                                const R* __restrict__ dh,
+                                                int ny, const R* __restrict__ dh,
                                                 const typename cpx<R>::type* __restrict__ G1,
                                                 typename cpx<R>::type* __restrict__ G2)
 {
@@ -329,10 +333,11 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     R* As = Ls;
     R* Bs = Ls + KS * MAP;
     const int half = NA / 2;
-    const int i0 = blockIdx.y * (MM / 2);
+    const unsigned lb = ny > 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int i0 = (int)(lb % (unsigned)ny) * (MM / 2);
     const int64_t r = blockIdx.z;
     const int64_t ncols = nb * half;
-    const int64_t g0 = (int64_t)blockIdx.x * (MN / 2);
+    const int64_t g0 = (int64_t)(lb / (unsigned)ny) * (MN / 2);
     const int64_t cbase = g0 / half;   // first (box, column) of the tile
     const int m0 = (int)(g0 - cbase * half);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -710,10 +715,11 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     }
     {
         const int ntSh = rs.nt_src / 2 + 1, ntDh = rs.nt_dst / 2 + 1;
-        dim3 grid(cdiv(nb * (NA / 2), MN / 2), cdiv(ntDh, MM / 2), nrhs);
+        const int ny = cdiv(ntDh, MM / 2);
+        dim3 grid(cdiv(nb * (NA / 2), MN / 2) * ny, 1, nrhs);
         with_ks<R>(p->tune.rs_slab[1], [&](auto t) {
             hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
-                               ntSh, ntDh, rs.ldh, (const R*)rs.dth_h, (const C*)G1, G2);
+                               ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, (const C*)G1, G2);
         });
         FFMM_LAUNCH_CHECK();
     }
