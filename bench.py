@@ -558,14 +558,17 @@ def main():
         ms64 = timed(lambda: p64.matvec(q64), max(3, args.steps // 2), 2)
         out64 = p64.matvec(q64).cpu().numpy()
         i64 = p64.info()
-        # per-stage times of the FP64 plan (every stage alone, as for FP32)
+        # per-stage times of the FP64 plan (every stage alone, P2P on the whole GPU, as for FP32)
+        tuned64 = p64.tuning()
+        p64.set_tuning(p2p_blocks_per_cu=0)
         p64.profile(True)
         for _ in range(3):
             p64.matvec(q64)
         prof64 = p64.profile_read()
         p64.profile(False)
+        p64.set_tuning(**tuned64)
         fp64 = {"value": n / (ms64 * 1e-3) / 1e6, "ms_per_step": ms64, "setup_s": s64,
-                "depth": i64["depth"], "eps": 1e-6, "tuning": p64.tuning(), "autotune_s": tune64_s,
+                "depth": i64["depth"], "eps": 1e-6, "tuning": tuned64, "autotune_s": tune64_s,
                 "stages_ms": {k: round(v[0] / 3, 4) for k, v in prof64.items()}}
         if not args.no_cpu:
             fp64["rel_err"] = float(np.linalg.norm(out64[tg] - ref) / np.linalg.norm(ref))

@@ -105,6 +105,8 @@ struct LevelData {
     int32_t* zhi = nullptr;
     int32_t* zpar = nullptr;        // parent of each entry (index in level l - 1)
     int32_t* zoct = nullptr;        // octant of zlo
+    int32_t* zsrc = nullptr;        // [n] per child: its pair's zlo when it is a zhi (its downward
+                                    // step-1 result is then zlo's times conj(rho)), else -1
     int32_t* zstart = nullptr;
     int32_t* zcount = nullptr;
     // (l < L) [nrows] complex: e^{i kappa cos(theta_n) a_{l+1}}, the ratio of the translations of

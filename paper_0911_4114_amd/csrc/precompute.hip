@@ -667,9 +667,13 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             }
             zct[pp] = (int)zlo.size() - zst[pp];
         }
+        std::vector<int> zsrc(Cl.n, -1);
+        for (size_t e = 0; e < zlo.size(); ++e)
+            if (zhi[e] >= 0) zsrc[zhi[e]] = zlo[e];
         Cl.nz = (int64_t)zlo.size();
         Cl.zlo = upload_int(p->arena, zlo, s);
         Cl.zhi = upload_int(p->arena, zhi, s);
+        Cl.zsrc = upload_int(p->arena, zsrc, s);
         Cl.zpar = upload_int(p->arena, zpar, s);
         Cl.zoct = upload_int(p->arena, zoct, s);
         Pl.zstart = upload_int(p->arena, zst, s);

@@ -248,8 +248,6 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
                                                int64_t nb_in, const int32_t* __restrict__ zpar,
                                                const int32_t* __restrict__ zoct,
                                                const int32_t* __restrict__ zlo,
-                                               const int32_t* __restrict__ zhi,
-                                               const typename cpx<R>::type* __restrict__ zrot,
                                                const typename cpx<R>::type* __restrict__ trans,
                                                typename cpx<R>::type* __restrict__ G1)
 {
@@ -284,22 +282,16 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
         }
         return;
     }
-    // lo's result as computed, hi's times conj(rho(n)); the pair indices are loaded first
-    const C z = zrot[row];
-    int lo[8], hi[8];
+    // lo's result only: hi's is lo's times conj(rho(n)), which the theta step applies as it reads
+    // lo's rows for hi; the pair indices are loaded first
+    int lo[8];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int64_t c = min(st.c0 + wr / 2 + T::rbox(lane, p), nt - 1);
-        lo[p] = zlo[c];
-        hi[p] = zhi[c];
-    }
+    for (int p = 0; p < 8; ++p) lo[p] = zlo[min(st.c0 + wr / 2 + T::rbox(lane, p), nt - 1)];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
         const int col = T::rcol(lane, p);
         if (st.c0 + wr / 2 + T::rbox(lane, p) >= nt || j0 + wc + col >= NA) continue;
-        const R x = T::re(acc, p), y = T::im(acc, p);
-        g[(uint64_t)(rb0 + (uint32_t)lo[p]) * bs + col] = cx<R>(x, y);
-        if (hi[p] >= 0) g[(uint64_t)(rb0 + (uint32_t)hi[p]) * bs + col] = cx<R>(x * z.x + y * z.y, y * z.x - x * z.y);
+        g[(uint64_t)(rb0 + (uint32_t)lo[p]) * bs + col] = cx<R>(T::re(acc, p), T::im(acc, p));
     }
 }
 
@@ -317,9 +309,13 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 // tiles of a column tile are consecutive logical blocks of one XCD, so that the tile's G1 columns,
 // read by every row tile, come from that XCD's L2 after the first (with one row tile the plain
 // order measured faster).
-template <class R, int KS>
+// ZP (downward pass): the column of a child that is the upper member of a z pair reads its pair's
+// lower member's G1 rows (step 1 wrote only those), times conj(rho(n)) on source row n.
+template <class R, int KS, bool ZP>
 __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, int ntSh, int ntDh, int ldh,
                                                 int ny, const R* __restrict__ dh,
+                                                const int32_t* __restrict__ zsrc,
+                                                const typename cpx<R>::type* __restrict__ zrot,
                                                 const typename cpx<R>::type* __restrict__ G1,
                                                 typename cpx<R>::type* __restrict__ G2)
 {
@@ -346,7 +342,7 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     const int64_t mat_off = (int64_t)ntSh * ldh;   // Do after De
     // this thread's staged column (phi_m of its box), row 0
     const C* sbase;
-    bool scol_ok;
+    bool scol_ok, zconj = false;
     {
         const int cc = tid & 31;
         int m = m0 + cc;
@@ -356,10 +352,18 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
             ++c;
         }
         scol_ok = g0 + cc < ncols;
+        if (ZP && scol_ok) {
+            const int zs = zsrc[c];
+            if (zs >= 0) {
+                c = zs;
+                zconj = true;
+            }
+        }
         sbase = scol_ok ? G1 + (r * nb + c) * rowsS * NA + m : G1;
     }
     V4<R> ra[QA];
     C rfa[QB], rfb[QB];   // F_m, F_{m + NPhi/2} of each staged row
+    C rz[ZP ? QB : 1];    // rho(n) of each staged row
     bool oka[QA], okb[QB];
     auto load = [&](int k0) {
         // A tile column c4: 0..31 are De rows i0.., 32..63 the same rows of Do
@@ -378,6 +382,7 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
             const int64_t row = (int64_t)min(tt, ntSh - 1) * NA;
             rfa[q] = sbase[row];
             rfb[q] = sbase[row + half];
+            if (ZP) rz[q] = zrot[min(tt, ntSh - 1)];
             okb[q] = tt < ntSh && scol_ok;
         }
     };
@@ -390,7 +395,12 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             const int o = ((tid >> 5) + 8 * q) * MBP + 2 * (tid & 31);
-            const C a = rfa[q], b = rfb[q];
+            C a = rfa[q], b = rfb[q];
+            if (ZP && zconj) {
+                const C z = rz[q];   // times conj(rho(n))
+                a = cx<R>(a.x * z.x + a.y * z.y, a.y * z.x - a.x * z.y);
+                b = cx<R>(b.x * z.x + b.y * z.y, b.y * z.x - b.x * z.y);
+            }
             const bool ok = okb[q];
             *(C*)&Bs[o] = cx<R>(ok ? a.x + b.x : R(0), ok ? a.y + b.y : R(0));
             *(C*)&Bs[KS * MBP + o] = cx<R>(ok ? a.x - b.x : R(0), ok ? a.y - b.y : R(0));
@@ -698,8 +708,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
                 hipLaunchKernelGGL((rs1_mfma<R, false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1,
                                    (const C*)S.sigM, S.K, S.n, (const int32_t*)nullptr,
-                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
-                                   (const C*)nullptr, (const C*)nullptr, G1);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr, G1);
             });
         } else {
             // one contraction per z pair of children
@@ -707,8 +716,8 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
             with_ks<R>(p->tune.rs_slab[0], [&](auto t) {
                 hipLaunchKernelGGL((rs1_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz, nb,
                                    rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1,
-                                   (const C*)S.sigL, S.K, S.n, Cl.zpar, Cl.zoct, Cl.zlo, Cl.zhi,
-                                   (const C*)S.zrot, (const C*)S.trans, G1);
+                                   (const C*)S.sigL, S.K, S.n, Cl.zpar, Cl.zoct, Cl.zlo, (const C*)S.trans,
+                                   G1);
             });
         }
         FFMM_LAUNCH_CHECK();
@@ -718,8 +727,14 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ny = cdiv(ntDh, MM / 2);
         dim3 grid(cdiv(nb * (NA / 2), MN / 2) * ny, 1, nrhs);
         with_ks<R>(p->tune.rs_slab[1], [&](auto t) {
-            hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA, rs.rows_src,
-                               ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, (const C*)G1, G2);
+            if (up)
+                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, false>), grid, dim3(NT), 0, s, nb, NA,
+                                   rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, (const int32_t*)nullptr,
+                                   (const C*)nullptr, (const C*)G1, G2);
+            else
+                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, true>), grid, dim3(NT), 0, s, nb, NA,
+                                   rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, Cl.zsrc,
+                                   (const C*)S.zrot, (const C*)G1, G2);
         });
         FFMM_LAUNCH_CHECK();
     }
