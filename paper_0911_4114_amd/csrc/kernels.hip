@@ -43,20 +43,21 @@ template <class C> __device__ inline C cmulconj(C a, C b)  // a * conj(b)
     return r;
 }
 
-// e^{i phase}. FP32: phase given in revolutions (hardware sine/cosine take revolutions);
-// FP64: phase in radians.
+// e^{i phase}, the phase given in revolutions. FP32: the hardware sine/cosine take revolutions.
 __device__ inline void cis(float rev, float& c, float& s)
 {
     s = __builtin_amdgcn_sinf(rev);
     c = __builtin_amdgcn_cosf(rev);
 }
-__device__ inline void cis(double rad, double& c, double& s) { sincos(rad, &s, &c); }
-
-// Phase scale: FP32 phases are carried in revolutions, FP64 phases in radians.
-template <class R> inline R phase_scale(double kappa)
+// FP64: the fraction of a revolution (exact) and sin/cos of pi times twice it, which needs no
+// reduction by multiples of pi/2 inexact in FP64
+__device__ inline void cis(double rev, double& c, double& s)
 {
-    return sizeof(R) == 4 ? (R)(kappa / kTwoPi) : (R)kappa;
+    sincospi(2.0 * __builtin_amdgcn_fract(rev), &s, &c);
 }
+
+// Phase scale: phases are carried in revolutions, kappa / 2 pi per unit of length.
+template <class R> inline R phase_scale(double kappa) { return (R)(kappa / kTwoPi); }
 
 // Knuth's TwoSum: s + e == a + b exactly.
 template <class R> __device__ inline void two_sum(R a, R b, R& s, R& e)
@@ -813,8 +814,8 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         const double u = r2s * y0;
         const double eh = fma(-0.5, u * y0, 0.5);
         const double rr = fma(u, eh, u);
-        double rev = rr * kappa_rev;
-        rev -= floor(rev);
+        // the phase in revolutions, reduced to [0, 1) by the hardware fraction (rev >= 0)
+        const double rev = __builtin_amdgcn_fract(rr * kappa_rev);
         cis((float)rev, c, s);
         inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
         if constexpr (GRAD) kr = (R)(kappa * rr);
@@ -827,7 +828,7 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         y = y * fma(-0.5 * r2s, y * y, 1.5);
         y = y * fma(-0.5 * r2s, y * y, 1.5);
         const double rr = r2s * y;
-        cis(kappa * rr, c, s);
+        cis(kappa_rev * rr, c, s);
         inv = ok ? y : 0.0;
         if constexpr (GRAD) kr = kappa * rr;
     }
