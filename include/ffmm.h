@@ -274,8 +274,8 @@ typedef struct {
                                    default 16, 32, 32, 16 */
     int32_t m2l_by_parent;      /* M2L form. 2 (default): by parent pairs, with the transfer
                                    functions of a chunk of m2l_chunk directions gathered into LDS
-                                   once per block and reused for a range of parents (FP32 plans;
-                                   FP64 plans take form 1); 1: by parent pairs, each source
+                                   once per block and reused for a range of parents (FP64 plans:
+                                   chunks of 32 pairs, whatever m2l_chunk); 1: by parent pairs, each source
                                    signature and transfer function read once per parent pair (2.5x
                                    faster than 0 at the leaves of a volume distribution); 0: one
                                    target box per block over its interaction list. Forms 1 and 2

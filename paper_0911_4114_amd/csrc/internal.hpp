@@ -178,7 +178,8 @@ struct ffmm_plan {
     ffmm_tuning tune{};             // launch configuration (ffmm_plan_set_tuning)
     int32_t* code_map = nullptr;    // [343] offset code -> 16 rep + g, -1 for the inner codes
     int32_t* m2l_rows = nullptr;    // [27][27] LDS row of 2D + e (-1: neighbours), [316] 16 rep + g,
-                                    // [27][8] mask of the source octants far from target octant ot
+                                    // [27][8] mask of the source octants far from target octant ot,
+                                    // [27][8] mask of the target octants far from source octant os
     int device = 0;                 // HIP device the plan was created on
     int n_cu = 0;                   // compute units of the plan's device
     void* scratch1 = nullptr;       // resample workspaces

@@ -480,17 +480,20 @@ __global__ __launch_bounds__(NTH) void m2lp_kernel(int K, int kchunks,
 // ------------------------------------------------------------------------------------------
 constexpr int kTW = 16;   // waves per block of m2lt_kernel
 
-template <int CW>
+// SM (FP64, whose 16-byte values would need 64 registers for the source signatures alone): the
+// loop runs source-octant-major, each source octant's two values loaded when it is reached and
+// applied to every present target octant far from it.
+template <class C, int CW, bool SM>
 __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
     int K, int Kp, int nranges, int64_t np, const int32_t* __restrict__ pslots,
     const int32_t* __restrict__ child_start, const int32_t* __restrict__ child_count,
     const int32_t* __restrict__ octant, const int32_t* __restrict__ rows,
     const int32_t* __restrict__ pairs, const int32_t* __restrict__ tperm,
-    const float2* __restrict__ T, const float2* __restrict__ M, float2* __restrict__ out,
+    const C* __restrict__ T, const C* __restrict__ M, C* __restrict__ out,
     int64_t nb, int nrhs)
 {
     static_assert(CW <= kWave && CW % 16 == 0, "chunk width");
-    __shared__ float2 Ts[kNumOffsets][CW];
+    __shared__ C Ts[kNumOffsets][CW];
     __shared__ int s_next;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int chunk = (int)(lb / (unsigned)nranges), range = (int)(lb % (unsigned)nranges);
@@ -503,13 +506,14 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
     // T_{g rep}(s_k1) = T_rep(s_{tperm[g][k1]}) of every transfer vector, row t of the table
     const int32_t* row_tix = rows + 27 * 27;
     const int32_t* farm = rows + 27 * 27 + kNumOffsets;
+    const int32_t* farmt = farm + 27 * 8;
     constexpr int kRowsPerWave = (kNumOffsets + kTW - 1) / kTW;
 #pragma unroll 5
     for (int j = 0; j < kRowsPerWave; ++j) {
         const int t = j * kTW + w;
         if (t < kNumOffsets) {
             const int tx = row_tix[t];
-            const float2 v = T[(int64_t)(tx >> 4) * K + tperm[(int64_t)(tx & (kNumSym - 1)) * K + k1]];
+            const C v = T[(int64_t)(tx >> 4) * K + tperm[(int64_t)(tx & (kNumSym - 1)) * K + k1]];
             if (lane < CW) Ts[t][lane] = v;
         }
     }
@@ -542,10 +546,10 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
 #pragma unroll
         for (int o = 0; o < 8; ++o) tm |= (__ballot(ot_l == o) != 0 ? 1 : 0) << o;
         for (int r = 0; r < nrhs; ++r) {
-            const float2* Mr = M + (int64_t)r * plane;
-            float2 acc[8][2];
+            const C* Mr = M + (int64_t)r * plane;
+            C acc[8][2];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) acc[o][0] = acc[o][1] = make_float2(0.f, 0.f);
+            for (int o = 0; o < 8; ++o) acc[o][0] = acc[o][1] = cz<C>();
             uint64_t occ = occ0;
             while (occ) {
                 const int D = __builtin_ctzll(occ);
@@ -554,21 +558,44 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
                 const int smD = __builtin_amdgcn_readlane(sm, D);
                 const int32_t* pr = rows + 27 * D;
                 const int32_t* fm = farm + 8 * D;
+                int rr[27];
+#pragma unroll
+                for (int e = 0; e < 27; ++e) rr[e] = pr[e];
+                if constexpr (SM) {
+                    const int32_t* ft = farmt + 8 * D;
+#pragma unroll
+                    for (int os = 0; os < 8; ++os) {
+                        if (!((smD >> os) & 1)) continue;
+                        const int m = ft[os] & tm;
+                        if (!m) continue;
+                        const int ci = sbD + __builtin_popcount(smD & ((1 << os) - 1));
+                        const C* mp = Mr + (int64_t)ci * K;
+                        const C m1 = mp[k1], m2 = mp[k2];
+#pragma unroll
+                        for (int ot = 0; ot < 8; ++ot) {
+                            if (!((m >> ot) & 1)) continue;
+                            __asm__ __volatile__("");
+                            const int e = ((os & 1) - (ot & 1) + 1) + 3 * (((os >> 1) & 1) - ((ot >> 1) & 1) + 1) +
+                                          9 * (((os >> 2) & 1) - ((ot >> 2) & 1) + 1);
+                            const int row = rr[e];
+                            cmac(acc[ot][0], m1, Ts[row][cl]);
+                            cmac(acc[ot][1], m2, Ts[kNumOffsets - 1 - row][cl]);
+                        }
+                    }
+                    continue;
+                }
                 // source signatures of the present octants at s and -s
-                float2 ms[8][2];
+                C ms[8][2];
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
-                    ms[o][0] = ms[o][1] = make_float2(0.f, 0.f);
+                    ms[o][0] = ms[o][1] = cz<C>();
                     if ((smD >> o) & 1) {
                         const int ci = sbD + __builtin_popcount(smD & ((1 << o) - 1));
-                        const float2* mp = Mr + (int64_t)ci * K;
+                        const C* mp = Mr + (int64_t)ci * K;
                         ms[o][0] = mp[k1];
                         ms[o][1] = mp[k2];
                     }
                 }
-                int rr[27];
-#pragma unroll
-                for (int e = 0; e < 27; ++e) rr[e] = pr[e];
                 // per present target octant, the present source octants far from it
 #pragma unroll
                 for (int ot = 0; ot < 8; ++ot) {
@@ -591,7 +618,7 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
                 for (int i = 0; i < tn; ++i) {
                     const int c = tb + i;
                     const int o = __builtin_amdgcn_readfirstlane(octant[c]);
-                    float2* op = out + (int64_t)r * plane + (int64_t)c * K;
+                    C* op = out + (int64_t)r * plane + (int64_t)c * K;
 #pragma unroll
                     for (int oo = 0; oo < 8; ++oo)
                         if (oo == o) {
@@ -1181,23 +1208,29 @@ void core_t(ffmm_plan* p, int nrhs, int stages, bool gradient, hipStream_t s)
                 continue;
             }
             const int kch = (Lv.K + 255) / 256;
-            if constexpr (sizeof(R) == 4) {
+            {
                 if (p->tune.m2l_by_parent == 2) {
                     // chunks of CW antipodal direction pairs; ranges of parents so that the grid
                     // is about one block per compute unit (a block holds most of a CU's LDS)
-                    const int cw = p->tune.m2l_chunk;
+                    // FP64: 32-pair chunks (the 16-byte values of 32 pairs fill the LDS as 64 do
+                    // in FP32), lanes 32..63 idle
+                    const int cw = sizeof(R) == 8 ? 32 : p->tune.m2l_chunk;
                     const int64_t nch = (Lv.Kp + cw - 1) / cw;
                     const int64_t nr = std::max<int64_t>(1, std::min<int64_t>(Pv.n, p->n_cu / std::max<int64_t>(nch, 1)));
                     const dim3 grid((unsigned)(nch * nr));
                     auto go = [&](auto kern) {
                         hipLaunchKernelGGL(kern, grid, dim3(kWave * kTW), 0, s, Lv.K, Lv.Kp, (int)nr, Pv.n,
                                            Pv.nb_slots, Pv.child_start, Pv.child_count, Lv.octant, p->m2l_rows,
-                                           Lv.pairs, Lv.tperm, (const float2*)Lv.transfer, (const float2*)Lv.sigM,
-                                           (float2*)Lv.sigL, Lv.n, nrhs);
+                                           Lv.pairs, Lv.tperm, (const C*)Lv.transfer, (const C*)Lv.sigM,
+                                           (C*)Lv.sigL, Lv.n, nrhs);
                     };
-                    if (cw == 64) go(m2lt_kernel<64>);
-                    else if (cw == 48) go(m2lt_kernel<48>);
-                    else go(m2lt_kernel<32>);
+                    if constexpr (sizeof(R) == 8) {
+                        go(m2lt_kernel<C, 32, true>);
+                    } else {
+                        if (cw == 64) go(m2lt_kernel<C, 64, false>);
+                        else if (cw == 48) go(m2lt_kernel<C, 48, false>);
+                        else go(m2lt_kernel<C, 32, false>);
+                    }
                     FFMM_LAUNCH_CHECK();
                     continue;
                 }

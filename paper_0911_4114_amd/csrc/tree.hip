@@ -758,7 +758,7 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s)
         // row of 2D + e (-1 where that vector joins neighbours), then per row its packed
         // representative and symmetry (16 rep + g), then per D and target octant the mask of the
         // source octants that are far from it
-        std::vector<int32_t> rows(27 * 27 + kNumOffsets + 27 * 8);
+        std::vector<int32_t> rows(27 * 27 + kNumOffsets + 2 * 27 * 8);
         {
             int32_t code_row[kNumCodes];
             int r = 0;
@@ -785,6 +785,14 @@ void build_tree(ffmm_plan* p, const double* d_points, hipStream_t s)
                         if (rows[27 * D + e] >= 0) m |= 1 << os;
                     }
                     rows[27 * 27 + kNumOffsets + 8 * D + ot] = m;
+                }
+            // the same relation per D and source octant os: bit ot set where ot is far from os
+            for (int D = 0; D < 27; ++D)
+                for (int os = 0; os < 8; ++os) {
+                    int m = 0;
+                    for (int ot = 0; ot < 8; ++ot)
+                        if ((rows[27 * 27 + kNumOffsets + 8 * D + ot] >> os) & 1) m |= 1 << ot;
+                    rows[27 * 27 + kNumOffsets + 27 * 8 + 8 * D + os] = m;
                 }
         }
         p->m2l_rows = p->arena.alloc_n<int32_t>(rows.size());

@@ -118,11 +118,13 @@ def test_transfer_tables_match_oracle(gpu):
 CASES["sphere65k_d5"] = (lambda: wl.sphere_points(65536), 177 * np.sqrt(65536 / 2 ** 20), 5)
 
 
-@pytest.mark.parametrize("name,by_parent", [("cube4096", 1), ("sphere6000", 1), ("sphere65k_d5", 1),
+@pytest.mark.parametrize("name,by_parent", [("cube4096", 2), ("sphere6000", 2), ("sphere65k_d5", 2),
+                                             ("cube4096", 1), ("sphere65k_d5", 1),
                                              ("cube4096", 0), ("sphere65k_d5", 0)])
 def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent):
     """Every stage of the FP64 path against the oracle; with by_parent the M2L runs by parent
-    pairs (the same sums in another order)."""
+    pairs (the same sums in another order): 2 with the transfer functions of 32-pair chunks in
+    LDS, source-octant-major, 1 reading them per parent pair, 0 per target box."""
     gen, kappa, depth = CASES[name]
     x = gen()
     q = wl.complex_normal(len(x))
