@@ -834,8 +834,10 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         // written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so R and the phase
         // kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the phase is reduced modulo 1 in
         // FP64 before the FP32 sine/cosine, and 1/R = y0 (1 + e) needs FP32 only.
+        // the pair of a point with itself (R = 0) is computed on a clamped R^2 and dropped by the
+        // select of 1/R below
         const bool ok = r2 > 0.0;
-        const double r2s = ok ? r2 : 1.0;
+        const double r2s = fmax(r2, 1e-30);
         const float y0f = __builtin_amdgcn_rsqf((float)r2s);
         const double y0 = (double)y0f;
         const double u = r2s * y0;
