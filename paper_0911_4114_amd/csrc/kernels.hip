@@ -744,9 +744,10 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                     } else {
 #pragma unroll
                         for (int u = 0; u < NR; ++u) {
-                            // explicit fused multiply-adds: the same rounding in every instantiation
-                            pre[u][0] += fma(c, sP[u][k], -(sn * sQ[u][k]));
-                            pim[u][0] += fma(c, sV[u][k], sn * sS[u][k]);
+                            // explicit fused multiply-adds, two per component: the same rounding
+                            // in every instantiation
+                            pre[u][0] = fma(-sn, sQ[u][k], fma(c, sP[u][k], pre[u][0]));
+                            pim[u][0] = fma(sn, sS[u][k], fma(c, sV[u][k], pim[u][0]));
                         }
                     }
                 }
