@@ -14,9 +14,9 @@
 // The children of one parent at octants o and o + 4 (same x and y, z apart by the child side)
 // have translations that differ by a factor rho(n) = e^{i kappa cos(theta_n) a_child}, constant
 // on each theta row; the row steps 1 and 5 do not mix rows, so such a z pair shares one
-// contraction: upward step 5 resamples row(lo) + rho row(hi) and translates it with lo's octant,
-// downward step 1 resamples the parent data times conj(E_oct(lo)) and hi's result is lo's times
-// conj(rho(n)).
+// contraction: upward the theta step writes row(lo) + rho row(hi) on each destination row, which
+// step 5 resamples once and translates with lo's octant; downward step 1 resamples the parent data
+// times conj(E_oct(lo)) and hi's result is lo's times conj(rho(n)).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -311,10 +311,17 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 // order measured faster).
 // ZP (downward pass): the column of a child that is the upper member of a z pair reads its pair's
 // lower member's G1 rows (step 1 wrote only those), times conj(rho(n)) on source row n.
-template <class R, int KS, bool ZP>
-__global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, int ntSh, int ntDh, int ldh,
-                                                int ny, const R* __restrict__ dh,
+// PAIR (upward pass): the columns are (z pair, phi_m, member), the two members of a pair adjacent
+// (a pair without an upper member has a zero column there), and each G2 row is written per pair:
+// row(lo) + rho(n') row(hi) on destination row n' (zrot of the destination level), the sum that
+// step 5 resamples and translates with lo's octant. nb then counts the pairs (G2 layout) and
+// nbox the children (G1 layout).
+template <class R, int KS, bool ZP, bool PAIR>
+__global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int64_t nbox, int NA, int rowsS, int ntSh, int ntDh,
+                                                int ldh, int ny, const R* __restrict__ dh,
                                                 const int32_t* __restrict__ zsrc,
+                                                const int32_t* __restrict__ zlo,
+                                                const int32_t* __restrict__ zhi,
                                                 const typename cpx<R>::type* __restrict__ zrot,
                                                 const typename cpx<R>::type* __restrict__ G1,
                                                 typename cpx<R>::type* __restrict__ G2)
@@ -332,10 +339,11 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     const unsigned lb = ny > 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int i0 = (int)(lb % (unsigned)ny) * (MM / 2);
     const int64_t r = blockIdx.z;
-    const int64_t ncols = nb * half;
+    const int64_t ncols = (PAIR ? 2 : 1) * nb * half;
     const int64_t g0 = (int64_t)(lb / (unsigned)ny) * (MN / 2);
-    const int64_t cbase = g0 / half;   // first (box, column) of the tile
-    const int m0 = (int)(g0 - cbase * half);
+    // first (box, column) of the tile; with PAIR, first (pair, column) of the tile's column pairs
+    const int64_t cbase = (PAIR ? g0 / 2 : g0) / half;
+    const int m0 = (int)((PAIR ? g0 / 2 : g0) - cbase * half);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const bool odd = wr != 0;
@@ -345,13 +353,18 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     bool scol_ok, zconj = false;
     {
         const int cc = tid & 31;
-        int m = m0 + cc;
+        int m = m0 + (PAIR ? cc / 2 : cc);
         int64_t c = cbase;
         while (m >= half) {
             m -= half;
             ++c;
         }
         scol_ok = g0 + cc < ncols;
+        if (PAIR && scol_ok) {
+            // the pair's member of this column (lo on even columns, hi on odd ones)
+            c = (cc & 1) ? zhi[c] : zlo[c];
+            scol_ok = c >= 0;
+        }
         if (ZP && scol_ok) {
             const int zs = zsrc[c];
             if (zs >= 0) {
@@ -359,7 +372,7 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
                 zconj = true;
             }
         }
-        sbase = scol_ok ? G1 + (r * nb + c) * rowsS * NA + m : G1;
+        sbase = scol_ok ? G1 + (r * nbox + c) * rowsS * NA + m : G1;
     }
     V4<R> ra[QA];
     C rfa[QB], rfb[QB];   // F_m, F_{m + NPhi/2} of each staged row
@@ -428,6 +441,31 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
 #pragma unroll
     for (int q = 0; q < 16; ++q) Ls[(wr + T::vrow(lane, q)) * MN + wc + T::vcol(lane, q)] = T::val(acc, q);
     __syncthreads();
+    if (PAIR) {
+        // per (destination row, column pair, half of the phi grid): the pair's sample
+        // row(lo) + rho row(hi); thread t takes outputs t, t + 256, .. of 32 x 16 x 2
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = tid + NT * i, pc = o & 15, hh = (o >> 4) & 1, tr = o >> 5;
+            const int tp = i0 + tr;
+            if (g0 + 2 * pc >= ncols || tp >= ntDh) continue;
+            int m = m0 + pc;
+            int64_t c = cbase;
+            while (m >= half) {
+                m -= half;
+                ++c;
+            }
+            const R sg = hh ? R(-1) : R(1);
+            const R* ur = Ls + tr * MN + 4 * pc;          // u' row: lo (re, im), hi (re, im)
+            const R* vr = Ls + (32 + tr) * MN + 4 * pc;   // v' row
+            const R lx = ur[0] + sg * vr[0], ly = ur[1] + sg * vr[1];
+            const R hx = ur[2] + sg * vr[2], hy = ur[3] + sg * vr[3];
+            const C z = zrot[tp];
+            G2[((r * nb + c) * ntDh + tp) * NA + m + (hh ? half : 0)] =
+                cx<R>(lx + z.x * hx - z.y * hy, ly + z.x * hy + z.y * hx);
+        }
+        return;
+    }
     const R sg = odd ? R(-1) : R(1);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -446,46 +484,29 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int NA, int rowsS, i
     }
 }
 
-// steps 4 + 5 staging: A = the destination row n' of G2 (on the common phi grid), B = the
-// Dirichlet block of the destination row. In the upward pass a tile row is a z pair (lo, hi) of
-// children: row(lo) + rho row(hi).
-template <class R, bool UP, int KS> struct Rs5Stage {
+// steps 4 + 5 staging: A = the destination row n' of G2 (on the common phi grid; upward, a G2
+// box is a z pair of children, already combined by the theta step), B = the Dirichlet block of
+// the destination row.
+template <class R, int KS> struct Rs5Stage {
     using C = typename cpx<R>::type;
-    static constexpr int QA = KS / 8, QB = KS / 16, QH = UP ? QA : 1;
+    static constexpr int QA = KS / 8, QB = KS / 16;
     int tid, NA, len, j0;
     int64_t cb, ce;
     const R* D;
-    C rho;
-    // row n' of this thread's tile rows (fixed over the slabs): lo and, upward, hi (lo's row when
-    // the pair has no hi)
-    const C* glo[QA];
-    const C* ghi[QH];
-    bool has_hi[QH];
-    // load() only issues the loads; store() forms the pair sums once they have landed, so that
-    // the next slab's loads stay in flight during the current slab's MFMAs
-    C rl[QA], rh[QH];
+    // row n' of this thread's tile rows (fixed over the slabs)
+    const C* g[QA];
+    C rl[QA];
     V4<R> rb[QB];
     bool oka[QA], okb[QB];
-    __device__ void init(const C* G2, int64_t nb, int64_t r, int ntDh, int row, const int32_t* zlo,
-                         const int32_t* zhi)
+    __device__ void init(const C* G2, int64_t nb, int64_t r, int ntDh, int row)
     {
         const uint32_t bs = (uint32_t)ntDh * NA;   // box stride
-        const C* g = G2 + (int64_t)row * NA;
+        const C* g0 = G2 + (int64_t)row * NA;
         const uint32_t rb0 = (uint32_t)(r * nb);
-        int lo[QA], hi[QA];
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int64_t c = min(cb + (tid + NT * q) / KS, ce - 1);
-            lo[q] = UP ? zlo[c] : (int)c;
-            if (UP) hi[q] = zhi[c];
-        }
-#pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            glo[q] = g + (uint64_t)(rb0 + (uint32_t)lo[q]) * bs;
-            if (UP) {
-                has_hi[q] = hi[q] >= 0;
-                ghi[q] = hi[q] >= 0 ? g + (uint64_t)(rb0 + (uint32_t)hi[q]) * bs : glo[q];
-            }
+            g[q] = g0 + (uint64_t)(rb0 + (uint32_t)c) * bs;
         }
     }
     __device__ void load(int k0)
@@ -493,9 +514,7 @@ template <class R, bool UP, int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
-            const int j = min(k0 + kk, NA - 1);
-            rl[q] = glo[q][j];
-            if (UP) rh[q] = ghi[q][j];
+            rl[q] = g[q][min(k0 + kk, NA - 1)];
             oka[q] = k0 + kk < NA && cb + bc < ce;
         }
 #pragma unroll
@@ -510,14 +529,8 @@ template <class R, bool UP, int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
-            R x = rl[q].x, y = rl[q].y;
-            if (UP && has_hi[q]) {
-                const C h = rh[q];
-                x += rho.x * h.x - rho.y * h.y;
-                y += rho.x * h.y + rho.y * h.x;
-            }
             const bool ok = oka[q];
-            *(C*)&As[(e % KS) * MAP + 2 * (e / KS)] = cx<R>(ok ? x : R(0), ok ? y : R(0));
+            *(C*)&As[(e % KS) * MAP + 2 * (e / KS)] = cx<R>(ok ? rl[q].x : R(0), ok ? rl[q].y : R(0));
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -535,8 +548,7 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     const R* __restrict__ d5, const typename cpx<R>::type* __restrict__ G2, int Kd,
     const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
     const int32_t* __restrict__ tile_pbeg, const int32_t* __restrict__ tile_pend,
-    const int32_t* __restrict__ zlo, const int32_t* __restrict__ zhi, const int32_t* __restrict__ zoct,
-    const typename cpx<R>::type* __restrict__ zrot, const int32_t* __restrict__ zstart,
+    const int32_t* __restrict__ zoct, const int32_t* __restrict__ zstart,
     const int32_t* __restrict__ zcount, const typename cpx<R>::type* __restrict__ trans, int64_t nb_out,
     typename cpx<R>::type* __restrict__ out)
 {
@@ -563,7 +575,7 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     __shared__ int pz[2][BC];   // upward: zstart - cb and zcount of the tile's parents
     R* As = Ls;
     R* Bs = Ls + KS * MAP;
-    Rs5Stage<R, UP, KS> st;
+    Rs5Stage<R, KS> st;
     st.tid = tid;
     st.NA = NA;
     st.len = len;
@@ -571,8 +583,7 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     st.cb = cb;
     st.ce = ce;
     st.D = d5 + (int64_t)off * NA;
-    st.rho = UP ? zrot[row] : cx<R>(R(1), R(0));
-    st.init(G2, nb, r, ntD / 2 + 1, row, zlo, zhi);
+    st.init(G2, nb, r, ntD / 2 + 1, row);
     // upward: the pair ranges of the tile's parents, staged in LDS before the contraction
     int p0 = 0, npar = 0;
     const uint32_t rbo = (uint32_t)(r * nb_out);
@@ -726,15 +737,18 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         const int ntSh = rs.nt_src / 2 + 1, ntDh = rs.nt_dst / 2 + 1;
         const int ny = cdiv(ntDh, MM / 2);
         dim3 grid(cdiv(nb * (NA / 2), MN / 2) * ny, 1, nrhs);
+        // upward: two columns (the z pair's members) per pair and phi_m
+        dim3 gridz(cdiv(2 * Cl.nz * (NA / 2), MN / 2) * ny, 1, nrhs);
         with_ks<R>(p->tune.rs_slab[1], [&](auto t) {
             if (up)
-                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, false>), grid, dim3(NT), 0, s, nb, NA,
-                                   rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, (const int32_t*)nullptr,
-                                   (const C*)nullptr, (const C*)G1, G2);
+                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, false, true>), gridz, dim3(NT), 0, s,
+                                   Cl.nz, nb, NA, rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h,
+                                   (const int32_t*)nullptr, Cl.zlo, Cl.zhi, (const C*)D.zrot, (const C*)G1, G2);
             else
-                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, true>), grid, dim3(NT), 0, s, nb, NA,
-                                   rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, Cl.zsrc,
-                                   (const C*)S.zrot, (const C*)G1, G2);
+                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, true, false>), grid, dim3(NT), 0, s, nb,
+                                   nb, NA, rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, Cl.zsrc,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)S.zrot,
+                                   (const C*)G1, G2);
         });
         FFMM_LAUNCH_CHECK();
     }
@@ -746,11 +760,11 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
             // tiles of whole parents' z pairs
             dim3 grid((unsigned)rs.nztiles, ntj * rs.rows_dst, nrhs);
             with_ks<R>(p->tune.rs_slab[2], [&](auto t) {
-                hipLaunchKernelGGL((rs5_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
-                                   rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5,
+                hipLaunchKernelGGL((rs5_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz,
+                                   NA, rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5,
                                    (const C*)G2, D.K, rs.ztile_begin, rs.ztile_end, rs.ztile_pbeg,
-                                   rs.ztile_pend, Cl.zlo, Cl.zhi, Cl.zoct, (const C*)D.zrot, D.zstart,
-                                   D.zcount, (const C*)D.trans, D.n, (C*)D.sigM);
+                                   rs.ztile_pend, Cl.zoct, D.zstart, D.zcount, (const C*)D.trans, D.n,
+                                   (C*)D.sigM);
             });
         } else {
             dim3 grid(cdiv(nb, BC), ntj * rs.rows_dst, nrhs);
@@ -759,7 +773,6 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
                                    rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5,
                                    (const C*)G2, D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
-                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr, D.n,
                                    (C*)D.sigL);
             });
