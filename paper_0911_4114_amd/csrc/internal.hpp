@@ -122,13 +122,21 @@ struct Resampler {
     int nt_src = 0, nt_dst = 0;
     int rows_src = 0, rows_dst = 0;
     int K_src = 0, K_dst = 0;
-    void* d1 = nullptr;             // step 1, per source row n: [N_phi,n][nphi_all] (j fastest)
+    // the row steps on half ranges of phi (u = x_m + x_{m+N/2}, v = x_m - x_{m+N/2} in, a + b and
+    // a - b out): step 1 per source row n [N_phi,n/2][2][ldj] (even then odd operator per source
+    // sample, destination sample fastest, ldj = nphi_all/2 rounded up to 4, zero padded),
+    // at element row_off[n] * ldj
+    void* d1h = nullptr;
+    int ldj = 0;
     // the theta step on half ranges (eqn. FourierSphereSym): operators for the even
     // and the odd parts of the phi columns, rows 0..N_theta/2 -> 0..N'_theta/2, each
     // [nt_src/2+1][ldh] (zero-padded), the even one first, the factor 1/2 of the split folded in
     void* dth_h = nullptr;
     int ldh = 0;
-    void* d5 = nullptr;             // step 5, per dest row n': [nphi_all][N'_phi,n'] (j' fastest)
+    // step 5 per destination row n': [nphi_all/2][2][ld'] with ld' = N'_phi,n'/2 rounded up to 4,
+    // at element d5h_off[n']
+    void* d5h = nullptr;
+    int32_t* d5h_off = nullptr;
     int32_t* d_src_row_off = nullptr;
     int32_t* d_src_nphi = nullptr;
     int32_t* d_dst_row_off = nullptr;

@@ -473,23 +473,57 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     rs.K_src = S.K;
     rs.K_dst = D.K;
     const int ldt = rs.nt_dst;   // row stride of the full-range theta operator (host only)
-    std::vector<double> d1((size_t)S.K * na), dth((size_t)rs.nt_src * ldt, 0.0), d5((size_t)D.K * na);
+    std::vector<double> dth((size_t)rs.nt_src * ldt, 0.0);
+    // Half-range row steps. Every row length is even (a multiple of 4) and the phi grids start at
+    // 0, so sample m + N/2 lies half a turn from sample m. With u_m = x_m + x_{m+N/2} (even modes
+    // only) and v_m = x_m - x_{m+N/2} (odd modes only), a resample y_j = sum_m D[m][j] x_m onto an
+    // even grid of N' points is y_j = a_j + b_j, y_{j+N'/2} = a_j - b_j for j < N'/2, with
+    // a = sum_m De[m][j] u_m, b = sum_m Do[m][j] v_m over m < N/2 and
+    // De, Do = (D[m][j] +- D[m + N/2][j]) / 2: the Dirichlet kernel's even frequencies are
+    // unchanged by the half-turn shift, its odd ones change sign. Each operator is stored as
+    // [N/2][2][ld] (De then Do per source sample, ld = N'/2 rounded up to a multiple of 4, zero
+    // padded), so that one 16-byte load serves four destination samples.
+    for (int v : S.par.nphi)
+        if (v % 2 != 0) fail(FFMM_ERR_INTERNAL, "odd quadrature row length");
+    for (int v : D.par.nphi)
+        if (v % 2 != 0) fail(FFMM_ERR_INTERNAL, "odd quadrature row length");
+    const int H = na / 2;
+    rs.ldj = (H + 3) / 4 * 4;
+    std::vector<double> d1h((size_t)S.K * rs.ldj, 0.0);
     for (int n = 0; n < S.nrows; ++n) {
-        const int len = S.par.nphi[n];
-        double* blk = &d1[(size_t)S.row_off[n] * na];
-        for (int m = 0; m < len; ++m)
-            for (int j = 0; j < na; ++j) blk[(size_t)m * na + j] = dirichlet(len, na, m, j);
+        const int len = S.par.nphi[n], h = len / 2;
+        double* blk = &d1h[(size_t)S.row_off[n] * rs.ldj];   // (row_off / 2) source pairs x 2 x ldj
+        for (int m = 0; m < h; ++m)
+            for (int j = 0; j < H; ++j) {
+                const double a = dirichlet(len, na, m, j), b = dirichlet(len, na, m + h, j);
+                blk[((size_t)m * 2 + 0) * rs.ldj + j] = 0.5 * (a + b);
+                blk[((size_t)m * 2 + 1) * rs.ldj + j] = 0.5 * (a - b);
+            }
+    }
+    std::vector<int> off5(D.nrows + 1, 0);
+    {
+        int64_t o = 0;
+        for (int n = 0; n < D.nrows; ++n) {
+            o += (int64_t)H * 2 * ((D.par.nphi[n] / 2 + 3) / 4 * 4);
+            if (o > INT32_MAX) fail(FFMM_ERR_UNSUPPORTED, "step-5 operator exceeds 2^31 elements");
+            off5[n + 1] = (int)o;
+        }
+    }
+    std::vector<double> d5h((size_t)off5[D.nrows], 0.0);
+    for (int n = 0; n < D.nrows; ++n) {
+        const int len = D.par.nphi[n], h = len / 2, ld = (h + 3) / 4 * 4;
+        double* blk = &d5h[(size_t)off5[n]];
+        for (int j = 0; j < H; ++j)
+            for (int jp = 0; jp < h; ++jp) {
+                const double a = dirichlet(na, len, j, jp), b = dirichlet(na, len, j + H, jp);
+                blk[((size_t)j * 2 + 0) * ld + jp] = 0.5 * (a + b);
+                blk[((size_t)j * 2 + 1) * ld + jp] = 0.5 * (a - b);
+            }
     }
     for (int t = 0; t < rs.nt_src; ++t)
         for (int tp = 0; tp < rs.nt_dst; ++tp)
             dth[(size_t)t * ldt + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
-    for (int n = 0; n < D.nrows; ++n) {
-        const int len = D.par.nphi[n];
-        double* blk = &d5[(size_t)D.row_off[n] * na];
-        for (int j = 0; j < na; ++j)
-            for (int jp = 0; jp < len; ++jp) blk[(size_t)j * len + jp] = dirichlet(na, len, j, jp);
-    }
-    upload_real<R>(p->arena, &rs.d1, d1, s);
+    upload_real<R>(p->arena, &rs.d1h, d1h, s);
     {
         // half-range theta operators: an even (odd) circle sequence x, x(N - t) = +-x(t), is
         // resampled by sum over the half range of x(t) (D[t][t'] +- D[N - t][t']), the rows t = 0,
@@ -509,7 +543,9 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
             }
         upload_real<R>(p->arena, &rs.dth_h, dh, s);
     }
-    upload_real<R>(p->arena, &rs.d5, d5, s);
+    upload_real<R>(p->arena, &rs.d5h, d5h, s);
+    off5.pop_back();
+    rs.d5h_off = upload_int(p->arena, off5, s);
     rs.d_src_row_off = S.d_row_off;
     rs.d_src_nphi = S.d_nphi;
     rs.d_dst_row_off = D.d_row_off;

@@ -7,6 +7,10 @@
 //   step 1      per source row n:  G1[c][n][j]  = sum_m D1_n[j][m] in_c(n, m),          j < NA
 //   steps 2+3   per column m < NA/2, on half ranges of theta (eqn. FourierSphereSym, below)
 //   steps 4+5   per destination row n': out_c(n', j') = sum_j D5_n'[j'][j] row_{c,n'}(j)
+// Steps 1 and 5 run on half ranges of phi (every row length is even and sample m + N/2 lies half a
+// turn from sample m): u = x_m + x_{m+N/2} carries the even modes, v = x_m - x_{m+N/2} the odd
+// ones, a = De u and b = Do v are contracted over m < N/2 in one MFMA tile (32 samples of each),
+// and the outputs are y_j = a_j + b_j, y_{j+N'/2} = a_j - b_j: half the work of the full rows.
 // UP (M2M, Section 2):   in_c = M^l_c; the parent signature is the sum over its children of
 //                         E_oct(c) * out_c, summed in LDS over whole parents per tile.
 // DOWN (L2L, Section 2): in_c = L^l_parent(c) * conj(E_oct(c)); out_c is added to L^{l+1}_c,
@@ -142,14 +146,17 @@ template <> struct V4<double> {
     }
 };
 
-// Shared main loop over one LDS slab buffer. Stage::load(k0) issues the global loads of the slab
-// starting at k0 into registers; Stage::store(As, Bs) writes them (zeroing invalid entries) once
-// they have landed. The next slab's loads are in flight during the current slab's MFMAs.
+// Shared main loop of the row steps over one LDS slab buffer. Stage::load(k0) issues the global
+// loads of the slab starting at k0 into registers; Stage::store(As, Bs) writes them (zeroing
+// invalid entries) once they have landed. The next slab's loads are in flight during the current
+// slab's MFMAs. The A slab is two [KS][MAP] halves, u then v: the waves of tile columns 0..31
+// (the even operator's block) read u, those of columns 32..63 (the odd operator's) read v.
 template <class R, int KS, class Stage>
 __device__ inline void mfma_mainloop(Stage& st, R* As, R* Bs, int K, typename MT<R>::acc_t& acc, int wr, int wc,
                                      int lane)
 {
     const int nslab = (K + KS - 1) / KS;
+    const R* Aw = As + (wc ? KS * MAP : 0);
     st.load(0);
     st.store(As, Bs);
     __syncthreads();
@@ -157,7 +164,7 @@ __device__ inline void mfma_mainloop(Stage& st, R* As, R* Bs, int K, typename MT
         const bool more = sl + 1 < nslab;
         if (more) st.load((sl + 1) * KS);
         const int kc = min(KS, K - sl * KS);
-        MT<R>::slab(As, Bs, acc, wr, wc, lane, (kc + 7) & ~7);
+        MT<R>::slab(Aw, Bs, acc, wr, wc, lane, (kc + 7) & ~7);
         if (more) {
             __syncthreads();   // every wave is done with this slab
             st.store(As, Bs);
@@ -166,22 +173,41 @@ __device__ inline void mfma_mainloop(Stage& st, R* As, R* Bs, int K, typename MT
     }
 }
 
-// step 1 staging: A = source row data of 32 boxes, or in the downward pass of 32 z pairs (lo, hi)
-// of children: the parent's data times conj(E_oct(lo)). B = the Dirichlet block of the row.
+// The row steps' epilogue exchange: each wave's 32 x 32 quadrant of the 64 x 64 block tile into
+// LDS (row = (box, re/im), column: 0..31 even part a, 32..63 odd part b of the same 32 samples)
+template <class R>
+__device__ inline void tile_to_lds(R* Ls, const typename MT<R>::acc_t& acc, int wr, int wc, int lane)
+{
+    using T = MT<R>;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Ls[(wr + T::vrow(lane, q)) * MN + wc + T::vcol(lane, q)] = T::val(acc, q);
+}
+
+// a + sg b of box b, sample i of the tile held in LDS by tile_to_lds
+template <class R>
+__device__ inline typename cpx<R>::type tile_out(const R* Ls, int b, int i, R sg)
+{
+    const R* r = Ls + 2 * b * MN + i;
+    return cx<R>(r[0] + sg * r[32], r[MN] + sg * r[MN + 32]);
+}
+
+// step 1 staging, on half ranges of phi: A = u, v of the source row data of 32 boxes (samples m
+// and m + N_phi,n/2), or in the downward pass of 32 z pairs (lo, hi) of children: the parent's data
+// times conj(E_oct(lo)). B = the row's even and odd operator blocks (32 samples each).
 template <class R, bool DOWN, int KS> struct Rs1Stage {
     using C = typename cpx<R>::type;
-    int tid, len, NA, j0;
+    int tid, h, H, ldj, j0;   // h, H: half the source row length and half NPhi
     int64_t c0, nb;
-    const R* d1;
+    const R* d1;              // the row's operator block
     int off;
     static constexpr int QA = KS / 8, QB = KS / 16, QT = DOWN ? QA : 1;
     // source row n of this thread's tile rows (fixed over the slabs), and downward the row of
     // the translation of lo's octant
     const C* gs[QA];
     const C* gt[QT];
-    // load() only issues the loads; store() applies conj(E) once they have landed, so that the
-    // next slab's loads stay in flight during the current slab's MFMAs
-    C ra[QA], rt[QT];
+    // load() only issues the loads; store() applies conj(E) and forms u, v once they have
+    // landed, so that the next slab's loads stay in flight during the current slab's MFMAs
+    C ra[QA], rc[QA], rt[QT], rtc[QT];
     V4<R> rb[QB];
     bool oka[QA], okb[QB];
     __device__ void init(const C* sig, int Ksrc, int64_t nb_in, int64_t r, const int32_t* zpar,
@@ -206,16 +232,20 @@ template <class R, bool DOWN, int KS> struct Rs1Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
-            const int k = min(k0 + kk, len - 1);
+            const int k = min(k0 + kk, h - 1);
             ra[q] = gs[q][k];
-            if (DOWN) rt[q] = gt[q][k];
-            oka[q] = k0 + kk < len && c0 + bc < nb;
+            rc[q] = gs[q][k + h];
+            if (DOWN) {
+                rt[q] = gt[q][k];
+                rtc[q] = gt[q][k + h];
+            }
+            oka[q] = k0 + kk < h && c0 + bc < nb;
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            const int e = tid + NT * q, kr = k0 + (e >> 4), j = j0 + 4 * (e & 15);
-            rb[q] = V4<R>::ld(d1 + (int64_t)(off + min(kr, len - 1)) * NA + (j < NA ? j : 0));
-            okb[q] = kr < len && j < NA;
+            const int e = tid + NT * q, kr = k0 + (e >> 4), c4 = 4 * (e & 15), j = j0 + (c4 & 31);
+            rb[q] = V4<R>::ld(d1 + ((int64_t)min(kr, h - 1) * 2 + (c4 >> 5)) * ldj + (j < ldj ? j : 0));
+            okb[q] = kr < h && j < H;
         }
     }
     __device__ void store(R* As, R* Bs)
@@ -223,13 +253,16 @@ template <class R, bool DOWN, int KS> struct Rs1Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
-            C v = ra[q];
+            C x = ra[q], y = rc[q];
             if (DOWN) {
-                const C t = rt[q];
-                v = cx<R>(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y);  // v conj(t)
+                const C t = rt[q], tc = rtc[q];   // times conj(E)
+                x = cx<R>(x.x * t.x + x.y * t.y, x.y * t.x - x.x * t.y);
+                y = cx<R>(y.x * tc.x + y.y * tc.y, y.y * tc.x - y.x * tc.y);
             }
             const bool ok = oka[q];
-            *(C*)&As[(e % KS) * MAP + 2 * (e / KS)] = cx<R>(ok ? v.x : R(0), ok ? v.y : R(0));
+            const int o = (e % KS) * MAP + 2 * (e / KS);
+            *(C*)&As[o] = cx<R>(ok ? x.x + y.x : R(0), ok ? x.y + y.y : R(0));
+            *(C*)&As[KS * MAP + o] = cx<R>(ok ? x.x - y.x : R(0), ok ? x.y - y.y : R(0));
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -239,11 +272,13 @@ template <class R, bool DOWN, int KS> struct Rs1Stage {
     }
 };
 
-// nt: the tile rows (boxes, or z pairs in the downward pass); nb: the boxes of the G1 layout
+// nt: the tile rows (boxes, or z pairs in the downward pass); nb: the boxes of the G1 layout.
+// Block (tile of 32 boxes, source row n, 32 samples j0.. of the first half of the common phi
+// grid): G1 samples j and j + NPhi/2.
 template <class R, bool DOWN, int KS>
-__global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows, int NA, int ntj,
+__global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows, int NA, int ldj, int ntj,
                                                const int32_t* __restrict__ row_off,
-                                               const int32_t* __restrict__ nphi, const R* __restrict__ d1,
+                                               const int32_t* __restrict__ nphi, const R* __restrict__ d1h,
                                                const typename cpx<R>::type* __restrict__ sig, int Ksrc,
                                                int64_t nb_in, const int32_t* __restrict__ zpar,
                                                const int32_t* __restrict__ zoct,
@@ -253,45 +288,47 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 {
     using C = typename cpx<R>::type;
     using T = MT<R>;
-    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * (MN / 2);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    __shared__ __align__(16) R As[KS * MAP];
-    __shared__ __align__(16) R Bs[KS * MBP];
+    constexpr int kL = 2 * KS * MAP + KS * MBP > MM * MN ? 2 * KS * MAP + KS * MBP : MM * MN;
+    __shared__ __align__(16) R Ls[kL];
+    R* As = Ls;
+    R* Bs = Ls + 2 * KS * MAP;
+    const int H = NA / 2;
     Rs1Stage<R, DOWN, KS> st;
     st.tid = tid;
-    st.len = nphi[row];
+    st.h = nphi[row] / 2;
     st.off = row_off[row];
-    st.NA = NA;
+    st.H = H;
+    st.ldj = ldj;
     st.j0 = j0;
     st.c0 = (int64_t)blockIdx.x * BC;
     st.nb = nt;
-    st.d1 = d1;
+    st.d1 = d1h + (int64_t)st.off * ldj;
     st.init(sig, Ksrc, nb_in, blockIdx.z, zpar, zoct, trans);
     typename T::acc_t acc = {};
-    mfma_mainloop<R, KS>(st, As, Bs, st.len, acc, wr, wc, lane);
-    const uint32_t rb0 = (uint32_t)(blockIdx.z * nb), bs = (uint32_t)rows * NA;   // box stride
-    C* g = G1 + (int64_t)row * NA + j0 + wc;
-    if (!DOWN) {
+    mfma_mainloop<R, KS>(st, As, Bs, st.h, acc, wr, wc, lane);
+    // downward: lo's result only (hi's is lo's times conj(rho(n)), which the theta step applies as
+    // it reads lo's rows for hi); the pair indices are loaded before the exchange
+    const int i = tid & 31, hh = (tid >> 5) & 1;
+    int dst[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int64_t c = st.c0 + wr / 2 + T::rbox(lane, p);
-            const int col = T::rcol(lane, p);
-            if (c < nt && j0 + wc + col < NA)
-                g[(uint64_t)(rb0 + (uint32_t)c) * bs + col] = cx<R>(T::re(acc, p), T::im(acc, p));
-        }
-        return;
+    for (int it = 0; it < 8; ++it) {
+        const int64_t c = min(st.c0 + (tid >> 6) + 4 * it, nt - 1);
+        dst[it] = DOWN ? zlo[c] : (int)c;
     }
-    // lo's result only: hi's is lo's times conj(rho(n)), which the theta step applies as it reads
-    // lo's rows for hi; the pair indices are loaded first
-    int lo[8];
+    tile_to_lds<R>(Ls, acc, wr, wc, lane);
+    __syncthreads();
+    if (j0 + i >= H) return;
+    const uint32_t rb0 = (uint32_t)(blockIdx.z * nb), bs = (uint32_t)rows * NA;   // box stride
+    C* g = G1 + (int64_t)row * NA + j0 + i + (hh ? H : 0);
+    const R sg = hh ? R(-1) : R(1);
 #pragma unroll
-    for (int p = 0; p < 8; ++p) lo[p] = zlo[min(st.c0 + wr / 2 + T::rbox(lane, p), nt - 1)];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int col = T::rcol(lane, p);
-        if (st.c0 + wr / 2 + T::rbox(lane, p) >= nt || j0 + wc + col >= NA) continue;
-        g[(uint64_t)(rb0 + (uint32_t)lo[p]) * bs + col] = cx<R>(T::re(acc, p), T::im(acc, p));
+    for (int it = 0; it < 8; ++it) {
+        const int b = (tid >> 6) + 4 * it;
+        if (st.c0 + b >= nt) break;
+        g[(uint64_t)(rb0 + (uint32_t)dst[it]) * bs] = tile_out<R>(Ls, b, i, sg);
     }
 }
 
@@ -484,24 +521,24 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int64_t nbox, int NA
     }
 }
 
-// steps 4 + 5 staging: A = the destination row n' of G2 (on the common phi grid; upward, a G2
-// box is a z pair of children, already combined by the theta step), B = the Dirichlet block of
-// the destination row.
+// steps 4 + 5 staging, on half ranges of phi: A = u, v of the destination row n' of G2 (samples j
+// and j + NPhi/2 of the common phi grid; upward, a G2 box is a z pair of children, already
+// combined by the theta step), B = the row's even and odd operator blocks (32 samples each).
 template <class R, int KS> struct Rs5Stage {
     using C = typename cpx<R>::type;
     static constexpr int QA = KS / 8, QB = KS / 16;
-    int tid, NA, len, j0;
+    int tid, H, hp, ld, j0;   // H = NPhi/2; hp, ld: half the destination row length, its stride
     int64_t cb, ce;
-    const R* D;
+    const R* D;               // the row's operator block
     // row n' of this thread's tile rows (fixed over the slabs)
     const C* g[QA];
-    C rl[QA];
+    C rl[QA], rh[QA];
     V4<R> rb[QB];
     bool oka[QA], okb[QB];
     __device__ void init(const C* G2, int64_t nb, int64_t r, int ntDh, int row)
     {
-        const uint32_t bs = (uint32_t)ntDh * NA;   // box stride
-        const C* g0 = G2 + (int64_t)row * NA;
+        const uint32_t bs = (uint32_t)ntDh * (2 * H);   // box stride
+        const C* g0 = G2 + (int64_t)row * (2 * H);
         const uint32_t rb0 = (uint32_t)(r * nb);
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -514,14 +551,16 @@ template <class R, int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q, kk = e % KS, bc = e / KS;
-            rl[q] = g[q][min(k0 + kk, NA - 1)];
-            oka[q] = k0 + kk < NA && cb + bc < ce;
+            const int k = min(k0 + kk, H - 1);
+            rl[q] = g[q][k];
+            rh[q] = g[q][k + H];
+            oka[q] = k0 + kk < H && cb + bc < ce;
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            const int e = tid + NT * q, j = k0 + (e >> 4), jp = j0 + 4 * (e & 15);
-            rb[q] = V4<R>::ld(D + (int64_t)min(j, NA - 1) * len + (jp < len ? jp : 0));
-            okb[q] = j < NA && jp < len;
+            const int e = tid + NT * q, kr = k0 + (e >> 4), c4 = 4 * (e & 15), jp = j0 + (c4 & 31);
+            rb[q] = V4<R>::ld(D + ((int64_t)min(kr, H - 1) * 2 + (c4 >> 5)) * ld + (jp < ld ? jp : 0));
+            okb[q] = kr < H && jp < hp;
         }
     }
     __device__ void store(R* As, R* Bs)
@@ -529,8 +568,11 @@ template <class R, int KS> struct Rs5Stage {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + NT * q;
+            const C x = rl[q], y = rh[q];
             const bool ok = oka[q];
-            *(C*)&As[(e % KS) * MAP + 2 * (e / KS)] = cx<R>(ok ? rl[q].x : R(0), ok ? rl[q].y : R(0));
+            const int o = (e % KS) * MAP + 2 * (e / KS);
+            *(C*)&As[o] = cx<R>(ok ? x.x + y.x : R(0), ok ? x.y + y.y : R(0));
+            *(C*)&As[KS * MAP + o] = cx<R>(ok ? x.x - y.x : R(0), ok ? x.y - y.y : R(0));
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -540,13 +582,14 @@ template <class R, int KS> struct Rs5Stage {
     }
 };
 
-// UP: tiles of whole parents' z pairs (tile_begin/tile_end over the pairs, zstart/zcount each
-// parent's pairs); DOWN: tiles of 32 consecutive child boxes.
+// Block (tile, destination row n', 32 samples j0.. of the first half of the row): samples j' and
+// j' + N'_phi,n'/2. UP: tiles of whole parents' z pairs (tile_begin/tile_end over the pairs,
+// zstart/zcount each parent's pairs); DOWN: tiles of 32 consecutive child boxes.
 template <class R, bool UP, int KS>
 __global__ __launch_bounds__(NT) void rs5_mfma(
     int64_t nb, int NA, int ntD, int ntj, const int32_t* __restrict__ row_off, const int32_t* __restrict__ nphi,
-    const R* __restrict__ d5, const typename cpx<R>::type* __restrict__ G2, int Kd,
-    const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
+    const R* __restrict__ d5h, const int32_t* __restrict__ d5h_off, const typename cpx<R>::type* __restrict__ G2,
+    int Kd, const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
     const int32_t* __restrict__ tile_pbeg, const int32_t* __restrict__ tile_pend,
     const int32_t* __restrict__ zoct, const int32_t* __restrict__ zstart,
     const int32_t* __restrict__ zcount, const typename cpx<R>::type* __restrict__ trans, int64_t nb_out,
@@ -554,10 +597,10 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
 {
     using C = typename cpx<R>::type;
     using T = MT<R>;
-    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * MN;
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * (MN / 2);
     const int64_t r = blockIdx.z;
-    const int len = nphi[row], off = row_off[row];
-    if (j0 >= len) return;
+    const int len = nphi[row], hp = len / 2, off = row_off[row];
+    if (j0 >= hp) return;
     int64_t cb, ce;
     if (UP) {
         cb = tile_begin[blockIdx.x];
@@ -568,21 +611,23 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     }
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    // one LDS array: the A and B slabs during the contraction, then (upward) the translated
-    // pairs (32 x 64 complex) for the sums over each parent's pairs
-    constexpr int kL = (UP && KS * (MAP + MBP) < 2 * BC * MN) ? 2 * BC * MN : KS * (MAP + MBP);
+    // one LDS array: the A and B slabs during the contraction, then the tile for the exchange of
+    // the even and odd parts, then (upward) the translated pairs (32 x 64 complex) for the sums
+    // over each parent's pairs
+    constexpr int kL = 2 * KS * MAP + KS * MBP > MM * MN ? 2 * KS * MAP + KS * MBP : MM * MN;
     __shared__ __align__(16) R Ls[kL];
     __shared__ int pz[2][BC];   // upward: zstart - cb and zcount of the tile's parents
     R* As = Ls;
-    R* Bs = Ls + KS * MAP;
+    R* Bs = Ls + 2 * KS * MAP;
     Rs5Stage<R, KS> st;
     st.tid = tid;
-    st.NA = NA;
-    st.len = len;
+    st.H = NA / 2;
+    st.hp = hp;
+    st.ld = (hp + 3) & ~3;
     st.j0 = j0;
     st.cb = cb;
     st.ce = ce;
-    st.D = d5 + (int64_t)off * NA;
+    st.D = d5h + d5h_off[row];
     st.init(G2, nb, r, ntD / 2 + 1, row);
     // upward: the pair ranges of the tile's parents, staged in LDS before the contraction
     int p0 = 0, npar = 0;
@@ -596,60 +641,69 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
         }
     }
     typename T::acc_t acc = {};
-    mfma_mainloop<R, KS>(st, As, Bs, NA, acc, wr, wc, lane);
+    mfma_mainloop<R, KS>(st, As, Bs, NA / 2, acc, wr, wc, lane);
+    // this thread's outputs: sample i of the half hh (j' = j0 + i + hh hp) of boxes
+    // (tid >> 6) + 4 it, it < 8
+    const int i = tid & 31, hh = (tid >> 5) & 1;
+    const bool col_ok = j0 + i < hp;
+    const int jp = min(j0 + i, hp - 1) + (hh ? hp : 0);
+    const R sg = hh ? R(-1) : R(1);
     C ev[8];
     if (!UP) {
-        // add to I: the eight reads are issued before any write (columns clamped into the row)
-        C* o = out + off;
+        // add to I: the eight reads are issued before the exchange (boxes clamped into the tile)
+        C* o = out + off + jp;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int64_t c = min(cb + wr / 2 + T::rbox(lane, p), ce - 1);
-            ev[p] = o[(uint64_t)(rbo + (uint32_t)c) * (uint32_t)Kd + min(j0 + wc + T::rcol(lane, p), len - 1)];
+        for (int it = 0; it < 8; ++it) {
+            const int64_t c = min(cb + (tid >> 6) + 4 * it, ce - 1);
+            ev[it] = o[(uint64_t)(rbo + (uint32_t)c) * (uint32_t)Kd];
         }
+        tile_to_lds<R>(Ls, acc, wr, wc, lane);
+        __syncthreads();
+        if (!col_ok) return;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int64_t c = cb + wr / 2 + T::rbox(lane, p);
-            const int jp = j0 + wc + T::rcol(lane, p);
-            if (c < ce && jp < len)
-                o[(uint64_t)(rbo + (uint32_t)c) * (uint32_t)Kd + jp] =
-                    cx<R>(ev[p].x + T::re(acc, p), ev[p].y + T::im(acc, p));
+        for (int it = 0; it < 8; ++it) {
+            const int b = (tid >> 6) + 4 * it;
+            if (cb + b >= ce) break;
+            const C v = tile_out<R>(Ls, b, i, sg);
+            o[(uint64_t)(rbo + (uint32_t)(cb + b)) * (uint32_t)Kd] = cx<R>(ev[it].x + v.x, ev[it].y + v.y);
         }
         return;
     }
     {
-        // the octant of each result's pair, then its translation: all loads issued before use
+        // the octant of each output's pair, then its translation: all loads issued before use
         int oc[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) oc[p] = zoct[min(cb + wr / 2 + T::rbox(lane, p), ce - 1)];
-        const C* tr = trans + off;
+        for (int it = 0; it < 8; ++it) oc[it] = zoct[min(cb + (tid >> 6) + 4 * it, ce - 1)];
+        const C* tr = trans + off + jp;
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
-            ev[p] = tr[(uint32_t)oc[p] * (uint32_t)Kd + min(j0 + wc + T::rcol(lane, p), len - 1)];
+        for (int it = 0; it < 8; ++it) ev[it] = tr[(uint32_t)oc[it] * (uint32_t)Kd];
     }
-    // UP: translate each pair on the parent grid, then sum the pairs of every parent (the slabs
-    // are free after the main loop's last barrier)
-    C* S = (C*)Ls;   // 32 x 64 complex
+    tile_to_lds<R>(Ls, acc, wr, wc, lane);
+    __syncthreads();
+    // UP: translate each pair on the parent grid, then sum the pairs of every parent
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int bx = wr / 2 + T::rbox(lane, p), col = wc + T::rcol(lane, p);
-        const bool ok = j0 + col < len && cb + bx < ce;
-        const C t = ev[p];
-        const R x = T::re(acc, p), y = T::im(acc, p);
-        S[bx * MN + col] = cx<R>(ok ? x * t.x - y * t.y : R(0), ok ? x * t.y + y * t.x : R(0));
+    for (int it = 0; it < 8; ++it) {
+        const int b = (tid >> 6) + 4 * it;
+        const C v = tile_out<R>(Ls, b, i, sg), t = ev[it];
+        const bool ok = col_ok && cb + b < ce;
+        ev[it] = cx<R>(ok ? v.x * t.x - v.y * t.y : R(0), ok ? v.x * t.y + v.y * t.x : R(0));
     }
+    __syncthreads();   // every exchange value is read
+    C* S = (C*)Ls;     // 32 x 64 complex: [pair in tile][hh * 32 + i]
+#pragma unroll
+    for (int it = 0; it < 8; ++it) S[((tid >> 6) + 4 * it) * MN + hh * 32 + i] = ev[it];
     __syncthreads();
     for (int e = tid; e < MN * npar; e += NT) {
-        const int i = e % MN, pi = e / MN;
-        const int jj = j0 + i;
-        if (jj >= len) continue;
+        const int c64 = e % MN, pi = e / MN, ii = c64 & 31;
+        if (j0 + ii >= hp) continue;
         const int a = pz[0][pi], cnt = pz[1][pi];
         C sum = cx<R>(R(0), R(0));
         for (int c = a; c < a + cnt; ++c) {
-            const C v = S[c * MN + i];
+            const C v = S[c * MN + c64];
             sum.x += v.x;
             sum.y += v.y;
         }
-        out[(uint64_t)(rbo + (uint32_t)(p0 + pi)) * (uint32_t)Kd + off + jj] = sum;
+        out[(uint64_t)(rbo + (uint32_t)(p0 + pi)) * (uint32_t)Kd + off + j0 + ii + (c64 >> 5) * hp] = sum;
     }
 }
 
@@ -712,12 +766,12 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     const int NA = rs.nphi_all;
     const int64_t nb = Cl.n;
     {
-        const int ntj = cdiv(NA, MN);
+        const int ntj = cdiv(NA / 2, MN / 2);   // 32-sample tiles of the first half of the phi grid
         if (up) {
             dim3 grid(cdiv(nb, BC), ntj * rs.rows_src, nrhs);
             with_ks<R>(p->tune.rs_slab[0], [&](auto t) {
                 hipLaunchKernelGGL((rs1_mfma<R, false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, nb,
-                                   rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1,
+                                   rs.rows_src, NA, rs.ldj, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1h,
                                    (const C*)S.sigM, S.K, S.n, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr, G1);
             });
@@ -726,7 +780,7 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
             dim3 grid(cdiv(Cl.nz, BC), ntj * rs.rows_src, nrhs);
             with_ks<R>(p->tune.rs_slab[0], [&](auto t) {
                 hipLaunchKernelGGL((rs1_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz, nb,
-                                   rs.rows_src, NA, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1,
+                                   rs.rows_src, NA, rs.ldj, ntj, rs.d_src_row_off, rs.d_src_nphi, (const R*)rs.d1h,
                                    (const C*)S.sigL, S.K, S.n, Cl.zpar, Cl.zoct, Cl.zlo, (const C*)S.trans,
                                    G1);
             });
@@ -755,14 +809,14 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     {
         int mx = 0;
         for (int v : D.par.nphi) mx = std::max(mx, v);
-        const int ntj = cdiv(mx, MN);
+        const int ntj = cdiv(mx / 2, MN / 2);   // 32-sample tiles of the first half of the longest row
         if (up) {
             // tiles of whole parents' z pairs
             dim3 grid((unsigned)rs.nztiles, ntj * rs.rows_dst, nrhs);
             with_ks<R>(p->tune.rs_slab[2], [&](auto t) {
                 hipLaunchKernelGGL((rs5_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz,
-                                   NA, rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5,
-                                   (const C*)G2, D.K, rs.ztile_begin, rs.ztile_end, rs.ztile_pbeg,
+                                   NA, rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5h,
+                                   rs.d5h_off, (const C*)G2, D.K, rs.ztile_begin, rs.ztile_end, rs.ztile_pbeg,
                                    rs.ztile_pend, Cl.zoct, D.zstart, D.zcount, (const C*)D.trans, D.n,
                                    (C*)D.sigM);
             });
@@ -770,8 +824,8 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
             dim3 grid(cdiv(nb, BC), ntj * rs.rows_dst, nrhs);
             with_ks<R>(p->tune.rs_slab[3], [&](auto t) {
                 hipLaunchKernelGGL((rs5_mfma<R, false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
-                                   rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5,
-                                   (const C*)G2, D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5h,
+                                   rs.d5h_off, (const C*)G2, D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
                                    (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr, D.n,
                                    (C*)D.sigL);
