@@ -730,7 +730,7 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                 R pre[NR][NC], pim[NR][NC];
                 for (int u = 0; u < NR; ++u)
                     for (int a = 0; a < NC; ++a) pre[u][a] = pim[u][a] = 0;
-                for (int k = kb + sub; k < ke; k += g) {
+                auto term = [&](int k) {
                     R c, sn;
                     cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
                     if (GRAD) {
@@ -750,6 +750,13 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                             pim[u][0] = fma(sn, sS[u][k], fma(c, sV[u][k], pim[u][0]));
                         }
                     }
+                };
+                if (g == 1 && ke - kb == 8) {
+                    // one target per lane, a whole block of 8 pairs: unrolled, the same order
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) term(kb + k);
+                } else {
+                    for (int k = kb + sub; k < ke; k += g) term(k);
                 }
                 for (int u = 0; u < NR; ++u)
                     for (int a = 0; a < NC; ++a) {
@@ -831,10 +838,10 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         inv = ok ? y : 0.0f;
         if constexpr (GRAD) kr = (float)kappa * rf;
     } else if constexpr (sizeof(R) == 4) {
-        // y0 = hardware reciprocal square root of the FP32-rounded R^2; one Newton step in FP64
-        // written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so R and the phase
-        // kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the phase is reduced modulo 1 in
-        // FP64 before the FP32 sine/cosine, and 1/R = y0 (1 + e) needs FP32 only.
+        // y0 = hardware reciprocal square root of the FP32-rounded R^2 (about 1 ulp of FP32); one
+        // Newton step in FP64 written as R = u (1 + e), u = R^2 y0, e = (1 - u y0) / 2, so R and
+        // the phase kappa R / 2 pi stay FP64-accurate (relative ~1e-14); the phase is reduced
+        // modulo 1 in FP64 before the FP32 sine/cosine, and the FP32 1/R is y0 itself.
         // the pair of a point with itself (R = 0) is computed on a clamped R^2 and dropped by the
         // select of 1/R below
         const bool ok = r2 > 0.0;
@@ -847,7 +854,7 @@ __device__ __forceinline__ NearTerm<R, C, GRAD> pair_geom(double xi, double yi, 
         // the phase in revolutions, reduced to [0, 1) by the hardware fraction (rev >= 0)
         const double rev = __builtin_amdgcn_fract(rr * kappa_rev);
         cis((float)rev, c, s);
-        inv = ok ? fmaf(y0f, (float)eh, y0f) : 0.0f;
+        inv = ok ? y0f : 0.0f;
         if constexpr (GRAD) kr = (R)(kappa * rr);
     } else {
         // 1/R from the hardware reciprocal square root refined by two Newton steps
