@@ -167,9 +167,9 @@ def stage_work(info, stage):
         w["trans"] = 2.0 * n * kp
         w["bytes"] = n * (3 * rs + 2 * cs) + cs * nb[L] * K[L]
     elif stage == "p2p":
-        # per ordered pair: FP64 differences, R^2, R and the phase reduction; FP32 1/R, complex
-        # MAC; reciprocal square root, sine and cosine
-        w["flops"] = 26.0 * info["n_near_pairs"]
+        # per ordered pair: FP64 differences (3), R^2 (5), the Newton step for R (6) and the phase
+        # (1); FP32 e^{i kR}/R (2) and the complex MAC (8); reciprocal square root, sine and cosine
+        w["flops"] = 25.0 * info["n_near_pairs"]
         w["trans"] = 3.0 * info["n_near_pairs"]
         w["bytes"] = n * (24 + 2 * cs)
         w["peak"] = FP64_PEAK_TFLOPS
