@@ -680,9 +680,10 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
     const int64_t plane = nb * K;
     const C* Lb = L + r0 * plane + b * K;
     for (int t0 = 0; t0 < cnt; t0 += kWave) {
-        // g lanes per target split its pairs when the chunk has few targets
+        // g lanes per target split its pairs when the chunk has few targets (a power of two, so
+        // that a lane takes exactly 8 pairs of every block of 8 g)
         const int tcnt = min(kWave, cnt - t0);
-        const int g = kWave / tcnt;
+        const int g = 1 << (31 - __builtin_clz(kWave / tcnt));
         const int my = lane / g, sub = lane % g;
         const bool valid = my < tcnt;
         const int64_t i = s0 + t0 + (valid ? my : 0);
@@ -698,6 +699,13 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
         for (int k0 = 0; k0 < Kp; k0 += CH) {
             const int nk = min(CH, Kp - k0);
             wave_lds_sync();
+            // pairs past the chunk's end up to a multiple of 64 are zero: they add exactly nothing,
+            // so that every block of 8 g pairs runs whole
+            for (int k = nk + lane; k < ((nk + 63) & ~63); k += kWave) {
+                sx[k] = sy[k] = sz[k] = 0;
+#pragma unroll
+                for (int u = 0; u < NR; ++u) sP[u][k] = sQ[u][k] = sV[u][k] = sS[u][k] = 0;
+            }
             for (int k = lane; k < nk; k += kWave) {
                 const int k1 = pairs[2 * (k0 + k)], k2 = pairs[2 * (k0 + k) + 1];
                 sx[k] = dirs[3 * k1];
@@ -721,43 +729,37 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                 }
             }
             wave_lds_sync();
-            // each lane: plain sums over up to 8 of its pairs (16 directions), combined with TwoSum;
-            // blocks of 8 g pairs rounded down to a power of two, at most 64, so that they tile every
-            // chunk size alike and a right-hand side gets the same sums alone or in a group
-            const int B = min(64, 1 << (31 - __builtin_clz(8 * g)));
-            for (int kb = 0; kb < nk; kb += B) {
-                const int ke = min(kb + B, nk);
+            // each lane: plain sums over 8 of its pairs (16 directions), combined with TwoSum;
+            // blocks of 8 g pairs, at most 64, so that they tile every chunk size alike and a
+            // right-hand side gets the same sums alone or in a group
+            const int B = min(64, 8 * g);
+            auto term = [&](R (&pre)[NR][NC], R (&pim)[NR][NC], int k) {
+                R c, sn;
+                cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
+                if (GRAD) {
+                    // (-i kappa s)[c (u1 - u2) + i sn (u1 + u2)] = kappa s (Y - i X)
+                    const R X = c * sS[0][k] - sn * sV[0][k], Y = c * sQ[0][k] + sn * sP[0][k];
+                    const R sa[3] = {sx[k], sy[k], sz[k]};
+                    for (int a = 0; a < NC; ++a) {
+                        pre[0][a] += kappa * sa[a] * Y;
+                        pim[0][a] -= kappa * sa[a] * X;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < NR; ++u) {
+                        // explicit fused multiply-adds, two per component: the same rounding in
+                        // every instantiation
+                        pre[u][0] = fma(-sn, sQ[u][k], fma(c, sP[u][k], pre[u][0]));
+                        pim[u][0] = fma(sn, sS[u][k], fma(c, sV[u][k], pim[u][0]));
+                    }
+                }
+            };
+            // one block: the lane's plain sums, then TwoSum into its running sums
+            auto block = [&](auto&& body) {
                 R pre[NR][NC], pim[NR][NC];
                 for (int u = 0; u < NR; ++u)
                     for (int a = 0; a < NC; ++a) pre[u][a] = pim[u][a] = 0;
-                auto term = [&](int k) {
-                    R c, sn;
-                    cis(sx[k] * x + sy[k] * y + sz[k] * z, c, sn);
-                    if (GRAD) {
-                        // (-i kappa s)[c (u1 - u2) + i sn (u1 + u2)] = kappa s (Y - i X)
-                        const R X = c * sS[0][k] - sn * sV[0][k], Y = c * sQ[0][k] + sn * sP[0][k];
-                        const R sa[3] = {sx[k], sy[k], sz[k]};
-                        for (int a = 0; a < NC; ++a) {
-                            pre[0][a] += kappa * sa[a] * Y;
-                            pim[0][a] -= kappa * sa[a] * X;
-                        }
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < NR; ++u) {
-                            // explicit fused multiply-adds, two per component: the same rounding
-                            // in every instantiation
-                            pre[u][0] = fma(-sn, sQ[u][k], fma(c, sP[u][k], pre[u][0]));
-                            pim[u][0] = fma(sn, sS[u][k], fma(c, sV[u][k], pim[u][0]));
-                        }
-                    }
-                };
-                if (g == 1 && ke - kb == 8) {
-                    // one target per lane, a whole block of 8 pairs: unrolled, the same order
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) term(kb + k);
-                } else {
-                    for (int k = kb + sub; k < ke; k += g) term(k);
-                }
+                body(pre, pim);
                 for (int u = 0; u < NR; ++u)
                     for (int a = 0; a < NC; ++a) {
                         R e1, e2;
@@ -766,6 +768,25 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
                         ere[u][a] += e1;
                         eim[u][a] += e2;
                     }
+            };
+            // separate loops for one lane per target (stride 1: the LDS reads of consecutive
+            // pairs pair up) and for g lanes per target
+            if (g == 1) {
+                for (int kb = 0; kb < nk; kb += 8)
+                    block([&](R (&pre)[NR][NC], R (&pim)[NR][NC]) {
+#pragma unroll
+                        for (int kk = 0; kk < 8; ++kk) term(pre, pim, kb + kk);
+                    });
+            } else {
+                for (int kb = 0; kb < nk; kb += B)
+                    block([&](R (&pre)[NR][NC], R (&pim)[NR][NC]) {
+                        if (B == 8 * g) {
+#pragma unroll
+                            for (int kk = 0; kk < 8; ++kk) term(pre, pim, kb + sub + g * kk);
+                        } else {
+                            for (int k = kb + sub; k < kb + B; k += g) term(pre, pim, k);
+                        }
+                    });
             }
         }
         if (g > 1) {
