@@ -771,17 +771,20 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
             };
             // separate loops for one lane per target (stride 1: the LDS reads of consecutive
             // pairs pair up) and for g lanes per target
+            // (unrolled for one right-hand side only: with several, the unrolled block holds every
+            // staged value in registers and occupancy drops)
+            constexpr int kUnroll = NR == 1 ? 8 : 1;
             if (g == 1) {
                 for (int kb = 0; kb < nk; kb += 8)
                     block([&](R (&pre)[NR][NC], R (&pim)[NR][NC]) {
-#pragma unroll
+#pragma unroll kUnroll
                         for (int kk = 0; kk < 8; ++kk) term(pre, pim, kb + kk);
                     });
             } else {
                 for (int kb = 0; kb < nk; kb += B)
                     block([&](R (&pre)[NR][NC], R (&pim)[NR][NC]) {
                         if (B == 8 * g) {
-#pragma unroll
+#pragma unroll kUnroll
                             for (int kk = 0; kk < 8; ++kk) term(pre, pim, kb + sub + g * kk);
                         } else {
                             for (int k = kb + sub; k < kb + B; k += g) term(pre, pim, k);
