@@ -204,7 +204,7 @@ def stage_roofline(info, stage, ms):
 # is the one the counters were taken on, else null.
 TRAFFIC_FILES = {
     "p2p": ("profiles/traffic_p2p_fp32_sphere1M_k177.txt", "p2p_kernel<float, float2, false, false, 1>"),
-    "m2l": ("profiles/traffic_m2l_fp32_sphere1M_k177.txt", "m2lt_kernel<64>*"),
+    "m2l": ("profiles/traffic_m2l_fp32_sphere1M_k177.txt", "m2lt_kernel<float2, 64, false>*"),
 }
 
 
