@@ -105,6 +105,7 @@ struct LevelData {
     int32_t* zhi = nullptr;
     int32_t* zpar = nullptr;        // parent of each entry (index in level l - 1)
     int32_t* zoct = nullptr;        // octant of zlo
+    int32_t* zmp = nullptr;         // [nz + 1] children in the entries before each (1 or 2 each)
     int32_t* zsrc = nullptr;        // [n] per child: its pair's zlo when it is a zhi (its downward
                                     // step-1 result is then zlo's times conj(rho)), else -1
     int32_t* zstart = nullptr;
@@ -148,6 +149,7 @@ struct Resampler {
     int32_t* ztile_end = nullptr;
     int32_t* ztile_pbeg = nullptr;  // first parent of each tile
     int32_t* ztile_pend = nullptr;  // one past its last parent
+    int32_t* zcol_tile = nullptr;   // upward theta step: the z pair of each 32-column tile's first column
 };
 
 }  // namespace ffmm

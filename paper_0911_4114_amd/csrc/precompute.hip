@@ -454,17 +454,22 @@ void transfer_tables(ffmm_plan* p, LevelData& L, hipStream_t s)
     tmp.release();
 }
 
-template <class R>
-void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resampler& rs, hipStream_t s)
+// Common phi length of steps 1-5: the smaller of the two largest row lengths. Upward the source
+// rows fit on it without loss, downward the destination rows keep no mode it lacks, and the theta
+// step acts on each phi mode separately; on data with the doubled-sphere symmetry (every
+// signature) this gives the same operator as the largest row length of either grid.
+int common_nphi(const LevelData& S, const LevelData& D)
 {
-    // Common phi length of steps 1-5: the smaller of the two largest row lengths. Upward the source
-    // rows fit on it without loss, downward the destination rows keep no mode it lacks, and the
-    // theta step acts on each phi mode separately; on data with the doubled-sphere symmetry (every
-    // signature) this gives the same operator as the largest row length of either grid.
     int na_s = 0, na_d = 0;
     for (int v : S.par.nphi) na_s = std::max(na_s, v);
     for (int v : D.par.nphi) na_d = std::max(na_d, v);
-    const int na = std::min(na_s, na_d);
+    return std::min(na_s, na_d);
+}
+
+template <class R>
+void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resampler& rs, hipStream_t s)
+{
+    const int na = common_nphi(S, D);
     rs.nphi_all = na;
     rs.nt_src = S.par.ntheta;
     rs.nt_dst = D.par.ntheta;
@@ -722,6 +727,23 @@ void build_tables_t(ffmm_plan* p, hipStream_t s)
             pe[t] = zpar[te[t] - 1] + 1;
         }
         Resampler& ru = p->up[l];
+        // the upward theta step's columns: per pair and phi_m the members present (lo, or lo and
+        // hi side by side), so a pair takes NPhi/2 columns per member; each 32-column tile starts
+        // in the pair recorded for it
+        {
+            const int64_t half = common_nphi(Cl, Pl) / 2;
+            std::vector<int> zmp(zlo.size() + 1, 0);
+            for (size_t e = 0; e < zlo.size(); ++e) zmp[e + 1] = zmp[e] + (zhi[e] >= 0 ? 2 : 1);
+            const int64_t ncol = half * zmp.back();
+            std::vector<int> tp0((ncol + 31) / 32);
+            size_t e = 0;
+            for (size_t t = 0; t < tp0.size(); ++t) {
+                while (half * zmp[e + 1] <= 32 * (int64_t)t) ++e;
+                tp0[t] = (int)e;
+            }
+            Cl.zmp = upload_int(p->arena, zmp, s);
+            ru.zcol_tile = upload_int(p->arena, tp0, s);
+        }
         ru.nztiles = (int)tb.size();
         ru.ztile_begin = upload_int(p->arena, std::vector<int>(tb.begin(), tb.end()), s);
         ru.ztile_end = upload_int(p->arena, std::vector<int>(te.begin(), te.end()), s);

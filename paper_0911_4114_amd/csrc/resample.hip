@@ -348,17 +348,20 @@ __global__ __launch_bounds__(NT) void rs1_mfma(int64_t nt, int64_t nb, int rows,
 // order measured faster).
 // ZP (downward pass): the column of a child that is the upper member of a z pair reads its pair's
 // lower member's G1 rows (step 1 wrote only those), times conj(rho(n)) on source row n.
-// PAIR (upward pass): the columns are (z pair, phi_m, member), the two members of a pair adjacent
-// (a pair without an upper member has a zero column there), and each G2 row is written per pair:
-// row(lo) + rho(n') row(hi) on destination row n' (zrot of the destination level), the sum that
-// step 5 resamples and translates with lo's octant. nb then counts the pairs (G2 layout) and
-// nbox the children (G1 layout).
+// PAIR (upward pass): the columns run over the z pairs, per pair and phi_m its members present (lo,
+// or lo and hi side by side), so that pair e starts at column zmp[e] NPhi/2 (zmp counts the
+// children before it; zcol_tile[tile] is the pair of a tile's first column); each G2 row is written
+// per pair: row(lo) + rho(n') row(hi) on destination row n' (zrot of the destination level), the
+// sum that step 5 resamples and translates with lo's octant. nb then counts the pairs (G2 layout)
+// and nbox the children (G1 layout).
 template <class R, int KS, bool ZP, bool PAIR>
 __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int64_t nbox, int NA, int rowsS, int ntSh, int ntDh,
                                                 int ldh, int ny, const R* __restrict__ dh,
                                                 const int32_t* __restrict__ zsrc,
                                                 const int32_t* __restrict__ zlo,
                                                 const int32_t* __restrict__ zhi,
+                                                const int32_t* __restrict__ zmp,
+                                                const int32_t* __restrict__ zcol_tile,
                                                 const typename cpx<R>::type* __restrict__ zrot,
                                                 const typename cpx<R>::type* __restrict__ G1,
                                                 typename cpx<R>::type* __restrict__ G2)
@@ -376,31 +379,45 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int64_t nbox, int NA
     const unsigned lb = ny > 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int i0 = (int)(lb % (unsigned)ny) * (MM / 2);
     const int64_t r = blockIdx.z;
-    const int64_t ncols = (PAIR ? 2 : 1) * nb * half;
-    const int64_t g0 = (int64_t)(lb / (unsigned)ny) * (MN / 2);
-    // first (box, column) of the tile; with PAIR, first (pair, column) of the tile's column pairs
-    const int64_t cbase = (PAIR ? g0 / 2 : g0) / half;
-    const int m0 = (int)((PAIR ? g0 / 2 : g0) - cbase * half);
+    const int64_t ncols = nbox * half;
+    const unsigned tile = lb / (unsigned)ny;
+    const int64_t g0 = (int64_t)tile * (MN / 2);
+    // first (box, column) of the tile
+    const int64_t cbase = g0 / half;
+    const int m0 = (int)(g0 - cbase * half);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const bool odd = wr != 0;
     const int64_t mat_off = (int64_t)ntSh * ldh;   // Do after De
-    // this thread's staged column (phi_m of its box), row 0
+    // this thread's staged column (phi_m of its box), row 0; with PAIR also the column's pair, its
+    // phi_m, whether it holds hi, and whether the pair has two members
     const C* sbase;
     bool scol_ok, zconj = false;
+    int64_t zp = 0;
+    int zm = 0;
+    bool zhi_col = false, ztwo = false;
     {
         const int cc = tid & 31;
-        int m = m0 + (PAIR ? cc / 2 : cc);
+        int m = m0 + cc;
         int64_t c = cbase;
-        while (m >= half) {
-            m -= half;
-            ++c;
-        }
         scol_ok = g0 + cc < ncols;
-        if (PAIR && scol_ok) {
-            // the pair's member of this column (lo on even columns, hi on odd ones)
-            c = (cc & 1) ? zhi[c] : zlo[c];
-            scol_ok = c >= 0;
+        if (PAIR) {
+            if (scol_ok) {
+                const int64_t g = g0 + cc;
+                zp = zcol_tile[tile];
+                while ((int64_t)zmp[zp + 1] * half <= g) ++zp;
+                const int a = zmp[zp], local = (int)(g - (int64_t)a * half);
+                ztwo = zmp[zp + 1] - a == 2;
+                zm = ztwo ? local >> 1 : local;
+                zhi_col = ztwo && (local & 1);
+                m = zm;
+                c = zhi_col ? zhi[zp] : zlo[zp];
+            }
+        } else {
+            while (m >= half) {
+                m -= half;
+                ++c;
+            }
         }
         if (ZP && scol_ok) {
             const int zs = zsrc[c];
@@ -479,27 +496,27 @@ __global__ __launch_bounds__(NT) void rs3h_mfma(int64_t nb, int64_t nbox, int NA
     for (int q = 0; q < 16; ++q) Ls[(wr + T::vrow(lane, q)) * MN + wc + T::vcol(lane, q)] = T::val(acc, q);
     __syncthreads();
     if (PAIR) {
-        // per (destination row, column pair, half of the phi grid): the pair's sample
-        // row(lo) + rho row(hi); thread t takes outputs t, t + 256, .. of 32 x 16 x 2
+        // per (destination row, lo column, half of the phi grid): the pair's sample
+        // row(lo) + rho row(hi), or row(lo) alone; the thread's column is the one it staged, its
+        // rows (tid >> 6) + 4 i and its half (tid >> 5) & 1
+        if (!scol_ok || zhi_col) return;
+        const int cc = tid & 31, hh = (tid >> 5) & 1;
+        const R sg = hh ? R(-1) : R(1);
+        C* g2 = G2 + (r * nb + zp) * ntDh * NA + zm + (hh ? half : 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = tid + NT * i, pc = o & 15, hh = (o >> 4) & 1, tr = o >> 5;
-            const int tp = i0 + tr;
-            if (g0 + 2 * pc >= ncols || tp >= ntDh) continue;
-            int m = m0 + pc;
-            int64_t c = cbase;
-            while (m >= half) {
-                m -= half;
-                ++c;
+        for (int i = 0; i < 8; ++i) {
+            const int tr = (tid >> 6) + 4 * i, tp = i0 + tr;
+            if (tp >= ntDh) break;
+            const R* ur = Ls + tr * MN + 2 * cc;          // u' row: lo (re, im), then hi (re, im)
+            const R* vr = Ls + (32 + tr) * MN + 2 * cc;   // v' row
+            R x = ur[0] + sg * vr[0], y = ur[1] + sg * vr[1];
+            if (ztwo) {
+                const R hx = ur[2] + sg * vr[2], hy = ur[3] + sg * vr[3];
+                const C z = zrot[tp];
+                x += z.x * hx - z.y * hy;
+                y += z.x * hy + z.y * hx;
             }
-            const R sg = hh ? R(-1) : R(1);
-            const R* ur = Ls + tr * MN + 4 * pc;          // u' row: lo (re, im), hi (re, im)
-            const R* vr = Ls + (32 + tr) * MN + 4 * pc;   // v' row
-            const R lx = ur[0] + sg * vr[0], ly = ur[1] + sg * vr[1];
-            const R hx = ur[2] + sg * vr[2], hy = ur[3] + sg * vr[3];
-            const C z = zrot[tp];
-            G2[((r * nb + c) * ntDh + tp) * NA + m + (hh ? half : 0)] =
-                cx<R>(lx + z.x * hx - z.y * hy, ly + z.x * hy + z.y * hx);
+            g2[(int64_t)tp * NA] = cx<R>(x, y);
         }
         return;
     }
@@ -790,19 +807,19 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     {
         const int ntSh = rs.nt_src / 2 + 1, ntDh = rs.nt_dst / 2 + 1;
         const int ny = cdiv(ntDh, MM / 2);
+        // one column per child and phi_m < NPhi/2 (upward ordered by z pair)
         dim3 grid(cdiv(nb * (NA / 2), MN / 2) * ny, 1, nrhs);
-        // upward: two columns (the z pair's members) per pair and phi_m
-        dim3 gridz(cdiv(2 * Cl.nz * (NA / 2), MN / 2) * ny, 1, nrhs);
         with_ks<R>(p->tune.rs_slab[1], [&](auto t) {
             if (up)
-                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, false, true>), gridz, dim3(NT), 0, s,
+                hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, false, true>), grid, dim3(NT), 0, s,
                                    Cl.nz, nb, NA, rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h,
-                                   (const int32_t*)nullptr, Cl.zlo, Cl.zhi, (const C*)D.zrot, (const C*)G1, G2);
+                                   (const int32_t*)nullptr, Cl.zlo, Cl.zhi, Cl.zmp, rs.zcol_tile,
+                                   (const C*)D.zrot, (const C*)G1, G2);
             else
                 hipLaunchKernelGGL((rs3h_mfma<R, decltype(t)::value, true, false>), grid, dim3(NT), 0, s, nb,
                                    nb, NA, rs.rows_src, ntSh, ntDh, rs.ldh, ny, (const R*)rs.dth_h, Cl.zsrc,
-                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)S.zrot,
-                                   (const C*)G1, G2);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const int32_t*)nullptr, (const C*)S.zrot, (const C*)G1, G2);
         });
         FFMM_LAUNCH_CHECK();
     }
