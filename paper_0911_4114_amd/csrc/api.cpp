@@ -55,6 +55,7 @@ void DeviceArena::release()
 }
 
 void prepare_rel(ffmm_plan* p, hipStream_t s);
+void init_cis_table(hipStream_t s);
 
 StageScope::StageScope(ffmm_plan* plan, int st, hipStream_t stream) : p(plan), stage(st), s(stream)
 {
@@ -385,6 +386,7 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
             p->device = dev;
             FFMM_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         }
+        init_cis_table(s);
         if (opt.method == FFMM_METHOD_DIRECT) {
             build_direct(p, d_points, s);
         } else {

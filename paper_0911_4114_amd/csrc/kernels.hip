@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -49,11 +50,26 @@ __device__ inline void cis(float rev, float& c, float& s)
     s = __builtin_amdgcn_sinf(rev);
     c = __builtin_amdgcn_cosf(rev);
 }
-// FP64: the fraction of a revolution (exact) and sin/cos of pi times twice it, which needs no
-// reduction by multiples of pi/2 inexact in FP64
+// FP64: (cos, sin)(2 pi k / 256), k < 256, each correctly rounded (filled by init_cis_table for
+// the device a plan is created on)
+__device__ double2 g_cis256[256];
+
+// FP64 e^{2 pi i rev}: the fraction of a revolution (exact), split as k / 256 + r with k the nearest
+// integer to 256 fract(rev) and |r| <= 1/512 (both exact); (cos, sin) of 2 pi k / 256 from the
+// table, of x = 2 pi r (|x| <= pi/256) from their Taylor series to x^6 (the first omitted terms are
+// below 2e-20), joined by the angle-sum formulas with cos x - 1 kept apart, so that no digit of
+// the table values is lost.
 __device__ inline void cis(double rev, double& c, double& s)
 {
-    sincospi(2.0 * __builtin_amdgcn_fract(rev), &s, &c);
+    const double t = __builtin_amdgcn_fract(rev) * 256.0;
+    const double k = __builtin_rint(t);
+    const double x = (t - k) * (kTwoPi / 256.0);
+    const double2 e = g_cis256[(int)k & 255];
+    const double x2 = x * x;
+    const double sx = x * fma(x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double cm1 = x2 * fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
+    c = fma(-e.y, sx, fma(e.x, cm1, e.x));
+    s = fma(e.x, sx, fma(e.y, cm1, e.y));
 }
 
 // Phase scale: phases are carried in revolutions, kappa / 2 pi per unit of length.
@@ -771,9 +787,10 @@ __global__ __launch_bounds__(kWave * kWpb) void l2p_kernel(int Kp, const R* __re
             };
             // separate loops for one lane per target (stride 1: the LDS reads of consecutive
             // pairs pair up) and for g lanes per target
-            // (unrolled for one right-hand side only: with several, the unrolled block holds every
-            // staged value in registers and occupancy drops)
-            constexpr int kUnroll = NR == 1 ? 8 : 1;
+            // (unrolled for one right-hand side's potential only: with several right-hand sides or
+            // the gradient, the unrolled block holds every staged value in registers and occupancy
+            // drops)
+            constexpr int kUnroll = NR == 1 && !GRAD ? 8 : 1;
             if (g == 1) {
                 for (int kb = 0; kb < nk; kb += 8)
                     block([&](R (&pre)[NR][NC], R (&pim)[NR][NC]) {
@@ -1406,6 +1423,22 @@ void prepare_rel_t(ffmm_plan* p, hipStream_t s)
 }
 
 }  // namespace
+
+// The FP64 phase table, on the current device (from long-double values rounded once).
+void init_cis_table(hipStream_t s)
+{
+    static const std::vector<double2> tab = [] {
+        std::vector<double2> t(256);
+        const long double two_pi = 2.0L * std::acos(-1.0L);
+        for (int k = 0; k < 256; ++k) {
+            const long double a = two_pi * (long double)k / 256.0L;
+            t[k] = make_double2((double)std::cos(a), (double)std::sin(a));
+        }
+        return t;
+    }();
+    FFMM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_cis256), tab.data(), sizeof(double2) * tab.size(), 0,
+                                    hipMemcpyHostToDevice, s));
+}
 
 void prepare_rel(ffmm_plan* p, hipStream_t s)
 {
