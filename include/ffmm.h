@@ -87,6 +87,12 @@ typedef struct {
                                 revolutions of the phase (kappa 2 sqrt(3) a_L <= 16 pi), R^2 is
                                 rounded to FP32 and 1/R, R and the phase follow in FP32 (relative
                                 phase error ~1e-7; faster) */
+    int32_t quarter_nphi;    /* the common phi length of a level transition from which the resample's
+                                row steps run on quarter ranges of phi (Section 3.4's interpolation
+                                split by the two half-turn and reflection symmetries of the
+                                Dirichlet kernel: a quarter of the full contraction); 0 (default):
+                                96; a value >= 4 sets it (4: every transition). Same results to
+                                rounding either way. */
 } ffmm_options;
 
 /*

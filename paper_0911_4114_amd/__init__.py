@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("eps_safety", ctypes.c_double),
                 ("max_rhs", ctypes.c_int32), ("reduce_depth", ctypes.c_int32),
                 ("ell_override", ctypes.c_int32 * MAX_LEVELS), ("method", ctypes.c_int32),
-                ("best_effort", ctypes.c_int32), ("fast_near_phase", ctypes.c_int32)]
+                ("best_effort", ctypes.c_int32), ("fast_near_phase", ctypes.c_int32),
+                ("quarter_nphi", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -206,12 +207,14 @@ class Plan:
     through the library's allocator hooks) or None (the library's own hipMalloc).
     best_effort: build the plan even where eps is out of reach (low-frequency breakdown) instead
     of raising FfmmError with status -5. fast_near_phase: FP32 near-field phase form (see
-    ffmm_options).
+    ffmm_options). quarter_nphi: common phi length from which the resample's row steps run on
+    quarter ranges (None: the library's default).
     """
 
     def __init__(self, points, kappa, eps, precision="fp64", depth=None, max_leaf=64,
                  alpha=None, eps_safety=None, max_rhs=1, reduce_depth=True, ell_override=None,
-                 method="fmm", best_effort=False, fast_near_phase=False, allocator="torch"):
+                 method="fmm", best_effort=False, fast_near_phase=False, quarter_nphi=None,
+                 allocator="torch"):
         lib = load_library()
         if not (isinstance(points, torch.Tensor) and points.is_cuda):
             raise TypeError("points must be a CUDA tensor")
@@ -234,6 +237,7 @@ class Plan:
             o.ell_override[int(l)] = int(v)
         o.best_effort = 1 if best_effort else 0
         o.fast_near_phase = 1 if fast_near_phase else 0
+        o.quarter_nphi = 0 if quarter_nphi is None else int(quarter_nphi)
         if allocator == "torch":
             al = Allocator(ctypes.c_void_p(pts.device.index or 0), _TORCH_ALLOC, _TORCH_FREE)
             alp = ctypes.byref(al)

@@ -294,6 +294,7 @@ ffmm_status ffmm_options_default(ffmm_options* o)
     o->reduce_depth = 1;
     o->best_effort = 0;
     o->fast_near_phase = 0;
+    o->quarter_nphi = 0;
     g_last_error.clear();
     return FFMM_OK;
 }
@@ -361,6 +362,7 @@ ffmm_status ffmm_plan_create(const double* d_points, int64_t n, double kappa, do
         if (opt.best_effort != 0 && opt.best_effort != 1) fail(FFMM_ERR_INVALID_ARG, "best_effort must be 0 or 1");
         if (opt.fast_near_phase != 0 && opt.fast_near_phase != 1)
             fail(FFMM_ERR_INVALID_ARG, "fast_near_phase must be 0 or 1");
+        if (opt.quarter_nphi < 0) fail(FFMM_ERR_INVALID_ARG, "quarter_nphi must be >= 0");
         if (alloc && (!alloc->alloc || !alloc->free))
             fail(FFMM_ERR_INVALID_ARG, "allocator needs both its alloc and free hooks");
         int ndev = 0;

@@ -118,6 +118,10 @@ struct LevelData {
 };
 
 // Dense real Fourier-resample operators between two level quadratures (Section 3.4).
+// the common phi length from which the row steps run on quarter ranges unless the plan's options
+// set another (below it the 32-sample output tiles of a quarter range would stay mostly empty)
+constexpr int kQuarterMinNphi = 96;
+
 struct Resampler {
     int nphi_all = 0;               // common phi length: min of the two quadratures' largest rows
     int nt_src = 0, nt_dst = 0;
@@ -138,6 +142,16 @@ struct Resampler {
     // at element d5h_off[n']
     void* d5h = nullptr;
     int32_t* d5h_off = nullptr;
+    // quarter ranges of phi (the half-range parts split again by phi -> -phi) where nphi_all >=
+    // kQuarterMinNphi: step 1 per source row [N_phi,n/4 + 1][4][ldq] at element d1q_off[n], step 5
+    // per destination row [nphi_all/4 + 1][4][ld'] (ld' = N'_phi,n'/4 + 1 rounded up to 4) at
+    // element d5q_off[n']; channels S, A, Mv, P
+    bool quarter = false;
+    int ldq = 0;
+    void* d1q = nullptr;
+    void* d5q = nullptr;
+    int32_t* d1q_off = nullptr;
+    int32_t* d5q_off = nullptr;
     int32_t* d_src_row_off = nullptr;
     int32_t* d_src_nphi = nullptr;
     int32_t* d_dst_row_off = nullptr;

@@ -466,6 +466,37 @@ int common_nphi(const LevelData& S, const LevelData& D)
     return std::min(na_s, na_d);
 }
 
+// Quarter-range form of a row step y_j = sum_m D[m][j] x_m from N to M samples (both multiples of
+// 4, grids starting at 0; D the Dirichlet kernel of dirichlet()). The half-range parts u (even
+// modes) and v (odd modes) are split again by the reflection phi -> -phi, under which the kernel
+// is even: for m = 0..N/4, with h = N/2 and x taken modulo N,
+//   u_m = x_m + x_{m+h}, ub_m = x_{h-m} + x_{-m}, v_m = x_m - x_{m+h}, vb_m = x_{h-m} - x_{-m},
+//   us = u + ub, ua = u - ub, vm = v - vb, vp = v + vb,
+// and per output j = 0..M/4 the four sums S = Cs us, A = Ca ua, Mv = Cm vm, P = Cp vp give
+//   y_j = S + A + Mv + P, y_{j+M/2} = S + A - Mv - P, and for 0 < j < M/4
+//   y_{M/2-j} = S - A + P - Mv, y_{M-j} = S - A - P + Mv.
+// With De, Do the half-range operators (D[m][j] +- D[m+h][j]) / 2 and r = h - m (Do at r = h is
+// -Do at 0): Cs, Ca = (De[m] +- De[r]) / 2, Cm, Cp = (Do[m] -+ Do[r]) / 2, halved at the
+// reflection's fixed points m = 0 and m = N/4. Stored [N/4 + 1][4][ld] (channels S, A, Mv, P; ld
+// = M/4 + 1 rounded up to 4, zero padded): a quarter of the full operator's work.
+void quarter_block(int N, int M, int ld, double* blk)
+{
+    const int h = N / 2, q = N / 4, Q = M / 4;
+    auto de = [&](int m, int j) { return 0.5 * (dirichlet(N, M, m, j) + dirichlet(N, M, m + h, j)); };
+    auto dodd = [&](int m, int j) { return 0.5 * (dirichlet(N, M, m, j) - dirichlet(N, M, m + h, j)); };
+    for (int m = 0; m <= q; ++m) {
+        const int r = (h - m) % h;
+        const double wt = (m == 0 || m == q) ? 0.5 : 1.0;
+        for (int j = 0; j <= Q; ++j) {
+            const double e0 = de(m, j), e1 = de(r, j), o0 = dodd(m, j), o1 = m == 0 ? -dodd(0, j) : dodd(r, j);
+            blk[((size_t)m * 4 + 0) * ld + j] = wt * 0.5 * (e0 + e1);
+            blk[((size_t)m * 4 + 1) * ld + j] = wt * 0.5 * (e0 - e1);
+            blk[((size_t)m * 4 + 2) * ld + j] = wt * 0.5 * (o0 - o1);
+            blk[((size_t)m * 4 + 3) * ld + j] = wt * 0.5 * (o0 + o1);
+        }
+    }
+}
+
 template <class R>
 void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resampler& rs, hipStream_t s)
 {
@@ -529,6 +560,34 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
         for (int tp = 0; tp < rs.nt_dst; ++tp)
             dth[(size_t)t * ldt + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
     upload_real<R>(p->arena, &rs.d1h, d1h, s);
+    // quarter-range row steps where the common phi length makes the contractions long
+    bool mult4 = na % 4 == 0;
+    for (int v : S.par.nphi) mult4 = mult4 && v % 4 == 0;
+    for (int v : D.par.nphi) mult4 = mult4 && v % 4 == 0;
+    rs.quarter = mult4 && na >= (p->opt.quarter_nphi > 0 ? p->opt.quarter_nphi : kQuarterMinNphi);
+    if (rs.quarter) {
+        const int Q = na / 4;
+        rs.ldq = (Q + 1 + 3) / 4 * 4;
+        std::vector<int> o1(S.nrows), o5(D.nrows);
+        int64_t t1 = 0, t5 = 0;
+        for (int n = 0; n < S.nrows; ++n) {
+            o1[n] = (int)t1;
+            t1 += (int64_t)(S.par.nphi[n] / 4 + 1) * 4 * rs.ldq;
+        }
+        for (int n = 0; n < D.nrows; ++n) {
+            o5[n] = (int)t5;
+            t5 += (int64_t)(Q + 1) * 4 * ((D.par.nphi[n] / 4 + 1 + 3) / 4 * 4);
+        }
+        if (t1 > INT32_MAX || t5 > INT32_MAX) fail(FFMM_ERR_UNSUPPORTED, "quarter-range operator exceeds 2^31 elements");
+        std::vector<double> q1((size_t)t1, 0.0), q5((size_t)t5, 0.0);
+        for (int n = 0; n < S.nrows; ++n) quarter_block(S.par.nphi[n], na, rs.ldq, &q1[o1[n]]);
+        for (int n = 0; n < D.nrows; ++n)
+            quarter_block(na, D.par.nphi[n], (D.par.nphi[n] / 4 + 1 + 3) / 4 * 4, &q5[o5[n]]);
+        upload_real<R>(p->arena, &rs.d1q, q1, s);
+        upload_real<R>(p->arena, &rs.d5q, q5, s);
+        rs.d1q_off = upload_int(p->arena, o1, s);
+        rs.d5q_off = upload_int(p->arena, o5, s);
+    }
     {
         // half-range theta operators: an even (odd) circle sequence x, x(N - t) = +-x(t), is
         // resampled by sum over the half range of x(t) (D[t][t'] +- D[N - t][t']), the rows t = 0,

@@ -64,6 +64,7 @@ template <class R> struct MT;
 // k = lane / 32; register q holds row (q / 4) * 8 + (lane / 32) * 4 + q % 4, column lane % 32.
 template <> struct MT<float> {
     using acc_t = f32x16;
+    template <int LDB = MBP>
     __device__ static void slab(const float* __restrict__ As, const float* __restrict__ Bs, acc_t& acc, int wr,
                                 int wc, int lane, int kc)
     {
@@ -73,7 +74,7 @@ template <> struct MT<float> {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 a[u] = As[(k8 + 2 * u + kh) * MAP + wr + i];
-                b[u] = Bs[(k8 + 2 * u + kh) * MBP + wc + i];
+                b[u] = Bs[(k8 + 2 * u + kh) * LDB + wc + i];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], acc, 0, 0, 0);
@@ -98,6 +99,7 @@ template <> struct MT<double> {
     struct acc_t {
         f64x4 t[4];   // tile (ti, tj) at 2 ti + tj
     };
+    template <int LDB = MBP>
     __device__ static void slab(const double* __restrict__ As, const double* __restrict__ Bs, acc_t& acc,
                                 int wr, int wc, int lane, int kc)
     {
@@ -105,7 +107,7 @@ template <> struct MT<double> {
         for (int k4 = 0; k4 < kc; k4 += 4) {
             const int k = k4 + kq;
             const double a0 = As[k * MAP + wr + pi], a1 = As[k * MAP + wr + 16 + pi];
-            const double b0 = Bs[k * MBP + wc + i], b1 = Bs[k * MBP + wc + 16 + i];
+            const double b0 = Bs[k * LDB + wc + i], b1 = Bs[k * LDB + wc + 16 + i];
             acc.t[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.t[0], 0, 0, 0);
             acc.t[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.t[1], 0, 0, 0);
             acc.t[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.t[2], 0, 0, 0);
@@ -189,6 +191,224 @@ __device__ inline typename cpx<R>::type tile_out(const R* Ls, int b, int i, R sg
 {
     const R* r = Ls + 2 * b * MN + i;
     return cx<R>(r[0] + sg * r[32], r[MN] + sg * r[MN + 32]);
+}
+
+// ---- quarter ranges of phi (long rows): the half-range parts split again by phi -> -phi --------
+// A block tile: 32 boxes (64 rows) x 128 columns, the S, A, Mv and P sums of 32 output indices j;
+// the A operand is four [KS][MAP] slabs (us, ua, vm, vp), the B operand [KS][128] (the four
+// operator blocks side by side). The waves of column half wc compute channels 2 wc and 2 wc + 1.
+constexpr int MQ = 128;   // LDS row stride of the quarter-range B slab and exchange tile
+
+template <class R, int KS, class Stage>
+__device__ inline void mfma_mainloop_q(Stage& st, R* As, R* Bs, int K, typename MT<R>::acc_t (&acc)[2], int wr,
+                                       int wc, int lane)
+{
+    const int nslab = (K + KS - 1) / KS;
+    st.load(0);
+    st.store(As, Bs);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        const bool more = sl + 1 < nslab;
+        if (more) st.load((sl + 1) * KS);
+        const int kc = (min(KS, K - sl * KS) + 7) & ~7;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int ch = 2 * (wc != 0) + c;
+            MT<R>::template slab<MQ>(As + ch * KS * MAP, Bs + ch * 32, acc[c], wr, 0, lane, kc);
+        }
+        if (more) {
+            __syncthreads();
+            st.store(As, Bs);
+        }
+        __syncthreads();
+    }
+}
+
+// the two channel tiles of each wave into LDS: row (box, re/im), column channel * 32 + j
+template <class R>
+__device__ inline void tile_to_lds_q(R* Ls, const typename MT<R>::acc_t (&acc)[2], int wr, int wc, int lane)
+{
+    using T = MT<R>;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int col0 = (2 * (wc != 0) + c) * 32;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            Ls[(wr + T::vrow(lane, q)) * MQ + col0 + T::vcol(lane, q)] = T::val(acc[c], q);
+    }
+}
+
+// the four outputs of box b, index jj of the tile: y_j, y_{j+M/2}, y_{M/2-j}, y_{M-j}
+template <class R>
+__device__ inline void tile_out_q(const R* Ls, int b, int jj, typename cpx<R>::type (&y)[4])
+{
+    const R* r = Ls + 2 * b * MQ + jj;   // re row; the im row follows
+    const R sx = r[0], ax = r[32], mx = r[64], px = r[96];
+    const R sy = r[MQ], ay = r[MQ + 32], my = r[MQ + 64], py = r[MQ + 96];
+    y[0] = cx<R>(sx + ax + mx + px, sy + ay + my + py);
+    y[1] = cx<R>(sx + ax - mx - px, sy + ay - my - py);
+    y[2] = cx<R>(sx - ax + px - mx, sy - ay + py - my);
+    y[3] = cx<R>(sx - ax - px + mx, sy - ay - py + my);
+}
+
+// staging of the quarter-range channels from the samples m, m + h, h - m, -m (mod N) of a row of N
+// samples (h = N/2, 0 <= m <= N/4): us, ua, vm, vp as above
+template <class R>
+__device__ inline void quarter_channels(typename cpx<R>::type x0, typename cpx<R>::type x1,
+                                        typename cpx<R>::type x2, typename cpx<R>::type x3, bool ok, R* As,
+                                        int KSMAP, int o)
+{
+    using C = typename cpx<R>::type;
+    const R ux = x0.x + x1.x, uy = x0.y + x1.y, bx = x2.x + x3.x, by = x2.y + x3.y;
+    const R vx = x0.x - x1.x, vy = x0.y - x1.y, wx = x2.x - x3.x, wy = x2.y - x3.y;
+    *(C*)&As[o] = cx<R>(ok ? ux + bx : R(0), ok ? uy + by : R(0));
+    *(C*)&As[KSMAP + o] = cx<R>(ok ? ux - bx : R(0), ok ? uy - by : R(0));
+    *(C*)&As[2 * KSMAP + o] = cx<R>(ok ? vx - wx : R(0), ok ? vy - wy : R(0));
+    *(C*)&As[3 * KSMAP + o] = cx<R>(ok ? vx + wx : R(0), ok ? vy + wy : R(0));
+}
+
+// step 1 on quarter ranges: A = the source row data of 32 boxes (downward, z pairs: the parent's
+// data times conj(E_oct(lo))), B = the row's quarter-range operator block.
+template <class R, bool DOWN, int KS> struct Rs1QStage {
+    using C = typename cpx<R>::type;
+    static constexpr int QA = KS / 8, QB = KS / 8, QT = DOWN ? QA : 1;
+    int tid, N, h, q, ldq, j0, Qp1;   // source row: N samples, h = N/2, q = N/4; Qp1 = NPhi/4 + 1
+    int64_t c0, nb;
+    const R* d1;
+    int off;
+    const C* gs[QA];
+    const C* gt[QT];
+    C ra[QA][4], rt[QT][4];
+    V4<R> rb[QB];
+    bool oka[QA], okb[QB];
+    __device__ void init(const C* sig, int Ksrc, int64_t nb_in, int64_t r, const int32_t* zpar,
+                         const int32_t* zoct, const C* trans)
+    {
+        const uint32_t rb0 = (uint32_t)(r * nb_in);
+        int bi[QA], oi[QA];
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int64_t c = min(c0 + (tid + NT * u) / KS, nb - 1);
+            bi[u] = DOWN ? zpar[c] : (int)c;
+            if (DOWN) oi[u] = zoct[c];
+        }
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            gs[u] = sig + off + (uint64_t)(rb0 + (uint32_t)bi[u]) * (uint32_t)Ksrc;
+            if (DOWN) gt[u] = trans + off + (uint32_t)oi[u] * (uint32_t)Ksrc;
+        }
+    }
+    __device__ void load(int k0)
+    {
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int e = tid + NT * u, kk = e % KS, bc = e / KS;
+            const int m = min(k0 + kk, q);
+            const int i[4] = {m, m + h, h - m, m == 0 ? 0 : N - m};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                ra[u][a] = gs[u][i[a]];
+                if (DOWN) rt[u][a] = gt[u][i[a]];
+            }
+            oka[u] = k0 + kk <= q && c0 + bc < nb;
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            const int e = tid + NT * u, kr = k0 + (e >> 5), c4 = 4 * (e & 31), j = j0 + (c4 & 31);
+            rb[u] = V4<R>::ld(d1 + ((int64_t)min(kr, q) * 4 + (c4 >> 5)) * ldq + (j < ldq ? j : 0));
+            okb[u] = kr <= q && j < Qp1;
+        }
+    }
+    __device__ void store(R* As, R* Bs)
+    {
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int e = tid + NT * u;
+            C x[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                x[a] = ra[u][a];
+                if (DOWN) {
+                    const C t = rt[u][a];   // times conj(E)
+                    x[a] = cx<R>(x[a].x * t.x + x[a].y * t.y, x[a].y * t.x - x[a].x * t.y);
+                }
+            }
+            quarter_channels<R>(x[0], x[1], x[2], x[3], oka[u], As, KS * MAP, (e % KS) * MAP + 2 * (e / KS));
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            const int e = tid + NT * u;
+            rb[u].st(&Bs[(e >> 5) * MQ + 4 * (e & 31)], okb[u]);
+        }
+    }
+};
+
+// Block (tile of 32 boxes, source row n, output indices j0.. j0 + 31 of 0..NPhi/4): G1 samples j,
+// j + NPhi/2, NPhi/2 - j and NPhi - j.
+template <class R, bool DOWN, int KS>
+__global__ __launch_bounds__(NT) void rs1q_mfma(int64_t nt, int64_t nb, int rows, int NA, int ldq, int ntj,
+                                                const int32_t* __restrict__ row_off,
+                                                const int32_t* __restrict__ nphi, const R* __restrict__ d1q,
+                                                const int32_t* __restrict__ d1q_off,
+                                                const typename cpx<R>::type* __restrict__ sig, int Ksrc,
+                                                int64_t nb_in, const int32_t* __restrict__ zpar,
+                                                const int32_t* __restrict__ zoct,
+                                                const int32_t* __restrict__ zlo,
+                                                const typename cpx<R>::type* __restrict__ trans,
+                                                typename cpx<R>::type* __restrict__ G1)
+{
+    using C = typename cpx<R>::type;
+    using T = MT<R>;
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * 32;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    constexpr int kL = 4 * KS * MAP + KS * MQ > MM * MQ ? 4 * KS * MAP + KS * MQ : MM * MQ;
+    __shared__ __align__(16) R Ls[kL];
+    R* As = Ls;
+    R* Bs = Ls + 4 * KS * MAP;
+    const int Q = NA / 4, H = NA / 2;
+    Rs1QStage<R, DOWN, KS> st;
+    st.tid = tid;
+    st.N = nphi[row];
+    st.h = st.N / 2;
+    st.q = st.N / 4;
+    st.ldq = ldq;
+    st.j0 = j0;
+    st.Qp1 = Q + 1;
+    st.off = row_off[row];
+    st.c0 = (int64_t)blockIdx.x * BC;
+    st.nb = nt;
+    st.d1 = d1q + d1q_off[row];
+    st.init(sig, Ksrc, nb_in, blockIdx.z, zpar, zoct, trans);
+    typename T::acc_t acc[2] = {};
+    mfma_mainloop_q<R, KS>(st, As, Bs, st.q + 1, acc, wr, wc, lane);
+    // downward: lo's result only (hi's is lo's times conj(rho(n)), applied by the theta step)
+    const int jj = tid & 31, j = j0 + jj;
+    int dst[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int64_t c = min(st.c0 + (tid >> 5) + 8 * it, nt - 1);
+        dst[it] = DOWN ? zlo[c] : (int)c;
+    }
+    tile_to_lds_q<R>(Ls, acc, wr, wc, lane);
+    __syncthreads();
+    if (j > Q) return;
+    const uint32_t rb0 = (uint32_t)(blockIdx.z * nb), bs = (uint32_t)rows * NA;   // box stride
+    const bool inner = j > 0 && j < Q;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int b = (tid >> 5) + 8 * it;
+        if (st.c0 + b >= nt) break;
+        C y[4];
+        tile_out_q<R>(Ls, b, jj, y);
+        C* g = G1 + (uint64_t)(rb0 + (uint32_t)dst[it]) * bs + (int64_t)row * NA;
+        g[j] = y[0];
+        g[j + H] = y[1];
+        if (inner) {
+            g[H - j] = y[2];
+            g[NA - j] = y[3];
+        }
+    }
 }
 
 // step 1 staging, on half ranges of phi: A = u, v of the source row data of 32 boxes (samples m
@@ -724,6 +944,203 @@ __global__ __launch_bounds__(NT) void rs5_mfma(
     }
 }
 
+// steps 4 + 5 on quarter ranges: A = the destination row n' of G2 (samples m, m + NPhi/2,
+// NPhi/2 - m, -m of the common phi grid; upward a G2 box is a z pair), B = the row's quarter-range
+// operator block.
+template <class R, int KS> struct Rs5QStage {
+    using C = typename cpx<R>::type;
+    static constexpr int QA = KS / 8, QB = KS / 8;
+    int tid, NA, H, q, ld, j0, Qp1;   // q = NPhi/4; Qp1 = N'_phi,n'/4 + 1, ld its stride
+    int64_t cb, ce;
+    const R* D;
+    const C* g[QA];
+    C ra[QA][4];
+    V4<R> rb[QB];
+    bool oka[QA], okb[QB];
+    __device__ void init(const C* G2, int64_t nb, int64_t r, int ntDh, int row)
+    {
+        const uint32_t bs = (uint32_t)ntDh * NA;   // box stride
+        const C* g0 = G2 + (int64_t)row * NA;
+        const uint32_t rb0 = (uint32_t)(r * nb);
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int64_t c = min(cb + (tid + NT * u) / KS, ce - 1);
+            g[u] = g0 + (uint64_t)(rb0 + (uint32_t)c) * bs;
+        }
+    }
+    __device__ void load(int k0)
+    {
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int e = tid + NT * u, kk = e % KS, bc = e / KS;
+            const int m = min(k0 + kk, q);
+            const int i[4] = {m, m + H, H - m, m == 0 ? 0 : NA - m};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ra[u][a] = g[u][i[a]];
+            oka[u] = k0 + kk <= q && cb + bc < ce;
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            const int e = tid + NT * u, kr = k0 + (e >> 5), c4 = 4 * (e & 31), j = j0 + (c4 & 31);
+            rb[u] = V4<R>::ld(D + ((int64_t)min(kr, q) * 4 + (c4 >> 5)) * ld + (j < ld ? j : 0));
+            okb[u] = kr <= q && j < Qp1;
+        }
+    }
+    __device__ void store(R* As, R* Bs)
+    {
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int e = tid + NT * u;
+            quarter_channels<R>(ra[u][0], ra[u][1], ra[u][2], ra[u][3], oka[u], As, KS * MAP,
+                                (e % KS) * MAP + 2 * (e / KS));
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            const int e = tid + NT * u;
+            rb[u].st(&Bs[(e >> 5) * MQ + 4 * (e & 31)], okb[u]);
+        }
+    }
+};
+
+// Block (tile, destination row n', output indices j0.. j0 + 31 of 0..N'_phi,n'/4): samples j',
+// j' + N'/2, N'/2 - j' and N' - j' of the row. UP: tiles of whole parents' z pairs, the translated
+// pairs summed per parent in LDS; DOWN: tiles of 32 children, added to I.
+template <class R, bool UP, int KS>
+__global__ __launch_bounds__(NT) void rs5q_mfma(
+    int64_t nb, int NA, int ntD, int ntj, const int32_t* __restrict__ row_off, const int32_t* __restrict__ nphi,
+    const R* __restrict__ d5q, const int32_t* __restrict__ d5q_off, const typename cpx<R>::type* __restrict__ G2,
+    int Kd, const int32_t* __restrict__ tile_begin, const int32_t* __restrict__ tile_end,
+    const int32_t* __restrict__ tile_pbeg, const int32_t* __restrict__ tile_pend,
+    const int32_t* __restrict__ zoct, const int32_t* __restrict__ zstart,
+    const int32_t* __restrict__ zcount, const typename cpx<R>::type* __restrict__ trans, int64_t nb_out,
+    typename cpx<R>::type* __restrict__ out)
+{
+    using C = typename cpx<R>::type;
+    using T = MT<R>;
+    const int row = blockIdx.y / ntj, j0 = (blockIdx.y % ntj) * 32;
+    const int64_t r = blockIdx.z;
+    const int len = nphi[row], Qd = len / 4, Hd = len / 2, off = row_off[row];
+    if (j0 > Qd) return;
+    int64_t cb, ce;
+    if (UP) {
+        cb = tile_begin[blockIdx.x];
+        ce = tile_end[blockIdx.x];
+    } else {
+        cb = (int64_t)blockIdx.x * BC;
+        ce = min(cb + BC, nb);
+    }
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    // one LDS array: the slabs, then the exchange tile, then (upward) the translated pairs
+    // (32 x 128 complex: the four outputs of 32 indices) for the sums over each parent's pairs
+    constexpr int kL = 4 * KS * MAP + KS * MQ > MM * MQ ? 4 * KS * MAP + KS * MQ : MM * MQ;
+    __shared__ __align__(16) R Ls[kL];
+    __shared__ int pz[2][BC];
+    R* As = Ls;
+    R* Bs = Ls + 4 * KS * MAP;
+    Rs5QStage<R, KS> st;
+    st.tid = tid;
+    st.NA = NA;
+    st.H = NA / 2;
+    st.q = NA / 4;
+    st.Qp1 = Qd + 1;
+    st.ld = (Qd + 1 + 3) & ~3;
+    st.j0 = j0;
+    st.cb = cb;
+    st.ce = ce;
+    st.D = d5q + d5q_off[row];
+    st.init(G2, nb, r, ntD / 2 + 1, row);
+    int p0 = 0, npar = 0;
+    const uint32_t rbo = (uint32_t)(r * nb_out);
+    if (UP) {
+        p0 = tile_pbeg[blockIdx.x];
+        npar = tile_pend[blockIdx.x] - p0;
+        if (tid < npar) {
+            pz[0][tid] = zstart[p0 + tid] - (int)cb;
+            pz[1][tid] = zcount[p0 + tid];
+        }
+    }
+    typename T::acc_t acc[2] = {};
+    mfma_mainloop_q<R, KS>(st, As, Bs, NA / 4 + 1, acc, wr, wc, lane);
+    // this thread's index jj (j' = j0 + jj) for boxes (tid >> 5) + 8 it, it < 4: outputs at
+    // j', j' + N'/2 and, for 0 < j' < N'/4, N'/2 - j' and N' - j'
+    const int jj = tid & 31, j = min(j0 + jj, Qd);
+    const bool col_ok = j0 + jj <= Qd, inner = j > 0 && j < Qd;
+    const int pos[4] = {j, j + Hd, inner ? Hd - j : j, inner ? len - j : j + Hd};
+    C ev[4][4];
+    if (!UP) {
+        // add to I: the reads issued before the exchange (boxes clamped into the tile)
+        C* o = out + off;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int64_t c = min(cb + (tid >> 5) + 8 * it, ce - 1);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ev[it][a] = o[(uint64_t)(rbo + (uint32_t)c) * (uint32_t)Kd + pos[a]];
+        }
+        tile_to_lds_q<R>(Ls, acc, wr, wc, lane);
+        __syncthreads();
+        if (!col_ok) return;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int b = (tid >> 5) + 8 * it;
+            if (cb + b >= ce) break;
+            C y[4];
+            tile_out_q<R>(Ls, b, jj, y);
+            C* ob = o + (uint64_t)(rbo + (uint32_t)(cb + b)) * (uint32_t)Kd;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (a < 2 || inner) ob[pos[a]] = cx<R>(ev[it][a].x + y[a].x, ev[it][a].y + y[a].y);
+        }
+        return;
+    }
+    {
+        // the octant of each output's pair, then its translations: all loads issued before use
+        int oc[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) oc[it] = zoct[min(cb + (tid >> 5) + 8 * it, ce - 1)];
+        const C* tr = trans + off;
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ev[it][a] = tr[(uint32_t)oc[it] * (uint32_t)Kd + pos[a]];
+    }
+    tile_to_lds_q<R>(Ls, acc, wr, wc, lane);
+    __syncthreads();
+    // UP: translate each pair on the parent grid, then sum the pairs of every parent
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int b = (tid >> 5) + 8 * it;
+        C y[4];
+        tile_out_q<R>(Ls, b, jj, y);
+        const bool ok = col_ok && cb + b < ce;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const C t = ev[it][a];
+            ev[it][a] = cx<R>(ok ? y[a].x * t.x - y[a].y * t.y : R(0), ok ? y[a].x * t.y + y[a].y * t.x : R(0));
+        }
+    }
+    __syncthreads();   // every exchange value is read
+    C* S = (C*)Ls;     // 32 x 128 complex: [pair in tile][a * 32 + jj]
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) S[((tid >> 5) + 8 * it) * MQ + a * 32 + jj] = ev[it][a];
+    __syncthreads();
+    for (int e = tid; e < MQ * npar; e += NT) {
+        const int c128 = e % MQ, pi = e / MQ, a = c128 >> 5, jx = j0 + (c128 & 31);
+        if (jx > Qd || (a >= 2 && (jx == 0 || jx == Qd))) continue;
+        const int p = a == 0 ? jx : a == 1 ? jx + Hd : a == 2 ? Hd - jx : len - jx;
+        const int a0 = pz[0][pi], cnt = pz[1][pi];
+        C sum = cx<R>(R(0), R(0));
+        for (int c = a0; c < a0 + cnt; ++c) {
+            const C v = S[c * MQ + c128];
+            sum.x += v.x;
+            sum.y += v.y;
+        }
+        out[(uint64_t)(rbo + (uint32_t)(p0 + pi)) * (uint32_t)Kd + off + p] = sum;
+    }
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -769,6 +1186,79 @@ template <class R, class F> void with_ks(int ks, F&& f)
         f(KsTag<64>{});
 }
 
+// the quarter-range kernels: FP32 slabs of 16 or 32, FP64 of 16 (their exchange tile and four A
+// slabs would exceed a block's LDS budget beyond)
+template <class R, class F> void with_ks_q(int ks, F&& f)
+{
+    if constexpr (sizeof(R) == 8)
+        f(KsTag<16>{});
+    else if (ks == 16)
+        f(KsTag<16>{});
+    else
+        f(KsTag<32>{});
+}
+
+template <class R>
+void run_resample_quarter(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s, bool step1)
+{
+    using C = typename cpx<R>::type;
+    const bool up = l_dst == l_src - 1;
+    Resampler& rs = up ? p->up[l_src] : p->down[l_src];
+    LevelData& S = p->lev[l_src];
+    LevelData& D = p->lev[l_dst];
+    LevelData& Cl = up ? S : D;
+    C* G1 = (C*)p->scratch1;
+    C* G2 = (C*)p->scratch2;
+    const int NA = rs.nphi_all;
+    const int64_t nb = Cl.n;
+    if (step1) {
+        const int ntj = cdiv(NA / 4 + 1, 32);
+        if (up) {
+            dim3 grid(cdiv(nb, BC), ntj * rs.rows_src, nrhs);
+            with_ks_q<R>(p->tune.rs_slab[0], [&](auto t) {
+                hipLaunchKernelGGL((rs1q_mfma<R, false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, nb,
+                                   rs.rows_src, NA, rs.ldq, ntj, rs.d_src_row_off, rs.d_src_nphi,
+                                   (const R*)rs.d1q, rs.d1q_off, (const C*)S.sigM, S.K, S.n,
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                   (const C*)nullptr, G1);
+            });
+        } else {
+            dim3 grid(cdiv(Cl.nz, BC), ntj * rs.rows_src, nrhs);
+            with_ks_q<R>(p->tune.rs_slab[0], [&](auto t) {
+                hipLaunchKernelGGL((rs1q_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz, nb,
+                                   rs.rows_src, NA, rs.ldq, ntj, rs.d_src_row_off, rs.d_src_nphi,
+                                   (const R*)rs.d1q, rs.d1q_off, (const C*)S.sigL, S.K, S.n, Cl.zpar, Cl.zoct,
+                                   Cl.zlo, (const C*)S.trans, G1);
+            });
+        }
+        FFMM_LAUNCH_CHECK();
+        return;
+    }
+    int mx = 0;
+    for (int v : D.par.nphi) mx = std::max(mx, v);
+    const int ntj = cdiv(mx / 4 + 1, 32);
+    if (up) {
+        dim3 grid((unsigned)rs.nztiles, ntj * rs.rows_dst, nrhs);
+        with_ks_q<R>(p->tune.rs_slab[2], [&](auto t) {
+            hipLaunchKernelGGL((rs5q_mfma<R, true, decltype(t)::value>), grid, dim3(NT), 0, s, Cl.nz, NA,
+                               rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5q, rs.d5q_off,
+                               (const C*)G2, D.K, rs.ztile_begin, rs.ztile_end, rs.ztile_pbeg, rs.ztile_pend,
+                               Cl.zoct, D.zstart, D.zcount, (const C*)D.trans, D.n, (C*)D.sigM);
+        });
+    } else {
+        dim3 grid(cdiv(nb, BC), ntj * rs.rows_dst, nrhs);
+        with_ks_q<R>(p->tune.rs_slab[3], [&](auto t) {
+            hipLaunchKernelGGL((rs5q_mfma<R, false, decltype(t)::value>), grid, dim3(NT), 0, s, nb, NA,
+                               rs.nt_dst, ntj, rs.d_dst_row_off, rs.d_dst_nphi, (const R*)rs.d5q, rs.d5q_off,
+                               (const C*)G2, D.K, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, (const int32_t*)nullptr, (const C*)nullptr, D.n,
+                               (C*)D.sigL);
+        });
+    }
+    FFMM_LAUNCH_CHECK();
+}
+
 template <class R>
 void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t s)
 {
@@ -782,7 +1272,9 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
     C* G2 = (C*)p->scratch2;
     const int NA = rs.nphi_all;
     const int64_t nb = Cl.n;
-    {
+    if (rs.quarter) {
+        run_resample_quarter<R>(p, l_src, l_dst, nrhs, s, true);
+    } else {
         const int ntj = cdiv(NA / 2, MN / 2);   // 32-sample tiles of the first half of the phi grid
         if (up) {
             dim3 grid(cdiv(nb, BC), ntj * rs.rows_src, nrhs);
@@ -823,7 +1315,9 @@ void run_resample_mfma(ffmm_plan* p, int l_src, int l_dst, int nrhs, hipStream_t
         });
         FFMM_LAUNCH_CHECK();
     }
-    {
+    if (rs.quarter) {
+        run_resample_quarter<R>(p, l_src, l_dst, nrhs, s, false);
+    } else {
         int mx = 0;
         for (int v : D.par.nphi) mx = std::max(mx, v);
         const int ntj = cdiv(mx / 2, MN / 2);   // 32-sample tiles of the first half of the longest row

@@ -118,20 +118,24 @@ def test_transfer_tables_match_oracle(gpu):
 CASES["sphere65k_d5"] = (lambda: wl.sphere_points(65536), 177 * np.sqrt(65536 / 2 ** 20), 5)
 
 
-@pytest.mark.parametrize("name,by_parent", [("cube4096", 2), ("sphere6000", 2), ("sphere65k_d5", 2),
-                                             ("cube4096", 1), ("sphere65k_d5", 1),
-                                             ("cube4096", 0), ("sphere65k_d5", 0)])
-def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent):
+@pytest.mark.parametrize("name,by_parent,quarter", [("cube4096", 2, None), ("sphere6000", 2, None),
+                                                     ("sphere65k_d5", 2, None), ("cube4096", 1, None),
+                                                     ("sphere65k_d5", 1, None), ("cube4096", 0, None),
+                                                     ("sphere65k_d5", 0, None), ("sphere6000", 2, 4),
+                                                     ("sphere65k_d5", 2, 4)])
+def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent, quarter):
     """Every stage of the FP64 path against the oracle; with by_parent the M2L runs by parent
     pairs (the same sums in another order): 2 with the transfer functions of 32-pair chunks in
-    LDS, source-octant-major, 1 reading them per parent pair, 0 per target box."""
+    LDS, source-octant-major, 1 reading them per parent pair, 0 per target box. quarter = 4 runs
+    every level transition's row steps on quarter ranges of phi (by default only transitions whose
+    common phi length reaches 96, which these cases do not)."""
     gen, kappa, depth = CASES[name]
     x = gen()
     q = wl.complex_normal(len(x))
-    log("fp64 stages %s by_parent=%d" % (name, by_parent))
+    log("fp64 stages %s by_parent=%d quarter=%s" % (name, by_parent, quarter))
     # forced depths: the 2^16-point sphere at depth 5 predicts 1.08e-6 at its leaf level, so the
     # plan is built best-effort (the measured error is checked against eps below)
-    p = ff.Plan(dev_points(x), kappa, 1e-6, depth=depth, best_effort=True)
+    p = ff.Plan(dev_points(x), kappa, 1e-6, depth=depth, best_effort=True, quarter_nphi=quarter)
     p.set_tuning(m2l_by_parent=by_parent)
     out = p.matvec(dev_complex(q)).cpu().numpy()
     info = p.info()
@@ -206,18 +210,20 @@ def test_fp32_matvec_meets_eps(gpu):
 TOL_FP32_BOX = 1e-4
 
 
-def test_fp32_stages_match_oracle(gpu):
+@pytest.mark.parametrize("quarter", [None, 4])
+def test_fp32_stages_match_oracle(gpu, quarter):
     """Every stage of the FP32 path against the FP64 oracle run on the plan's integer parameters,
     element by element: M^l and L^l at each level (the matrix-core resample kernels of the upward
     and downward passes, the FP32 transfer pass by parent pairs and per box, the half-range theta
     step), then the far field per point (L2P). 60000 sphere points at depth 4: leaves of up to 116
     points (several target chunks), quadratures of 5244 / 1824 / 912 directions (partial tiles; the
     transfer pass takes 128-direction blocks at levels 2 and 3 and 256-direction blocks at level
-    4)."""
+    4). quarter = 4: the row steps of every transition on quarter ranges of phi."""
     x = wl.sphere_points(60000, seed=5)
     kappa = 60.0
     q = wl.complex_normal(len(x)).astype(np.complex64).astype(complex)
-    p = ff.Plan(dev_points(x), kappa, 1e-4, precision="fp32", depth=4, reduce_depth=False)
+    p = ff.Plan(dev_points(x), kappa, 1e-4, precision="fp32", depth=4, reduce_depth=False,
+                quarter_nphi=quarter)
     info = p.info()
     log("fp32 stages: K %s leaves %d" % (info["K"][2:], info["n_boxes"][4]))
     o = OPlan(x, kappa, None, depth=info["depth"], quads=oracle_quads(p))
