@@ -91,7 +91,7 @@ typedef struct {
                                 row steps run on quarter ranges of phi (Section 3.4's interpolation
                                 split by the two half-turn and reflection symmetries of the
                                 Dirichlet kernel: a quarter of the full contraction); 0 (default):
-                                96; a value >= 4 sets it (4: every transition). Same results to
+                                64; a value >= 4 sets it (4: every transition). Same results to
                                 rounding either way. */
 } ffmm_options;
 

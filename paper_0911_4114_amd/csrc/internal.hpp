@@ -120,7 +120,7 @@ struct LevelData {
 // Dense real Fourier-resample operators between two level quadratures (Section 3.4).
 // the common phi length from which the row steps run on quarter ranges unless the plan's options
 // set another (below it the 32-sample output tiles of a quarter range would stay mostly empty)
-constexpr int kQuarterMinNphi = 96;
+constexpr int kQuarterMinNphi = 64;
 
 struct Resampler {
     int nphi_all = 0;               // common phi length: min of the two quadratures' largest rows

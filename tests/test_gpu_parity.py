@@ -128,7 +128,7 @@ def test_fp64_stages_and_matvec_match_oracle(gpu, name, by_parent, quarter):
     pairs (the same sums in another order): 2 with the transfer functions of 32-pair chunks in
     LDS, source-octant-major, 1 reading them per parent pair, 0 per target box. quarter = 4 runs
     every level transition's row steps on quarter ranges of phi (by default only transitions whose
-    common phi length reaches 96, which these cases do not)."""
+    common phi length reaches 64)."""
     gen, kappa, depth = CASES[name]
     x = gen()
     q = wl.complex_normal(len(x))
