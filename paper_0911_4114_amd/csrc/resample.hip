@@ -11,6 +11,9 @@
 // turn from sample m): u = x_m + x_{m+N/2} carries the even modes, v = x_m - x_{m+N/2} the odd
 // ones, a = De u and b = Do v are contracted over m < N/2 in one MFMA tile (32 samples of each),
 // and the outputs are y_j = a_j + b_j, y_{j+N'/2} = a_j - b_j: half the work of the full rows.
+// Where the common phi length is long (rs1q_mfma, rs5q_mfma), u and v are split again by the
+// reflection phi -> -phi, under which the kernel is even: four channels contracted over
+// m <= N/4 give the four samples j, j + N'/2, N'/2 - j and N' - j of each j <= N'/4.
 // UP (M2M, Section 2):   in_c = M^l_c; the parent signature is the sum over its children of
 //                         E_oct(c) * out_c, summed in LDS over whole parents per tile.
 // DOWN (L2L, Section 2): in_c = L^l_parent(c) * conj(E_oct(c)); out_c is added to L^{l+1}_c,
