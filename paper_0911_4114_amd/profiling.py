@@ -110,6 +110,29 @@ def traffic_summary(a):
     return "\n".join(lines)
 
 
+def traffic_total(a):
+    """HBM bytes per call of a kernel group: FETCH_SIZE and WRITE_SIZE (each scaled by the copy
+    probe) summed over every dispatch whose short name starts with one of the prefixes, divided
+    by the number of dispatches of the kernel that runs once per call (``--per``)."""
+    cf, _, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
+    cw, _, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
+    fs, ws = a.copy_bytes / (cf * 1024.0), a.copy_bytes / (cw * 1024.0)
+    total, calls = 0.0, set()
+    for path, counter, scale in ((a.fetch, "FETCH_SIZE", fs), (a.write, "WRITE_SIZE", ws)):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = short_name(r["Kernel_Name"])
+            if name == a.per:
+                calls.add((path, r["Dispatch_Id"]))
+            if any(name.startswith(k) for k in a.prefix):
+                total += 1024.0 * scale * float(r["Counter_Value"])
+    n = len(calls) // 2
+    if n == 0:
+        raise SystemExit("no dispatches of %s" % a.per)
+    return "calls: %d\nhbm_bytes_per_call: %.0f" % (n, total / n)
+
+
 def read_traffic(path):
     """key -> value (first token) of a summary written by ``traffic``."""
     out = {}
@@ -143,6 +166,18 @@ if __name__ == "__main__":
         ap.add_argument("--family", action="store_true",
                         help="--kernel is a name prefix; average over all matching dispatches")
         print(traffic_summary(ap.parse_args(sys.argv[2:])))
+    elif sys.argv[1] == "traffic-total":
+        ap = argparse.ArgumentParser(prog="profiling traffic-total")
+        ap.add_argument("--prefix", action="append", required=True,
+                        help="short-name prefix of the group's kernels (repeatable)")
+        ap.add_argument("--per", required=True, help="short name of a kernel run once per call")
+        ap.add_argument("--fetch", required=True)
+        ap.add_argument("--write", required=True)
+        ap.add_argument("--copy-fetch", required=True)
+        ap.add_argument("--copy-write", required=True)
+        ap.add_argument("--copy-bytes", type=int, required=True)
+        ap.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer")
+        print(traffic_total(ap.parse_args(sys.argv[2:])))
     elif sys.argv[1] == "trace":
         main(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25)
     elif sys.argv[1] == "streams":
