@@ -498,7 +498,10 @@ constexpr int kTW = 16;   // waves per block of m2lt_kernel
 
 // SM (FP64, whose 16-byte values would need 64 registers for the source signatures alone): the
 // loop runs source-octant-major, each source octant's two values loaded when it is reached and
-// applied to every present target octant far from it.
+// applied to every present target octant far from it. Its chunks hold 32 pairs (the table of 64
+// would not fit the LDS), so the two halves of a wave take the same pairs and split the target
+// octants by their x bit: half h serves the octants 2 j + h, whose offset row from a source octant
+// is that of 2 j minus one (one select per lane), and keeps their sums only.
 template <class C, int CW, bool SM>
 __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
     int K, int Kp, int nranges, int64_t np, const int32_t* __restrict__ pslots,
@@ -509,16 +512,20 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
     int64_t nb, int nrhs)
 {
     static_assert(CW <= kWave && CW % 16 == 0, "chunk width");
+    static_assert(!SM || 2 * CW == kWave, "the source-octant-major loop splits a wave in two halves");
     __shared__ C Ts[kNumOffsets][CW];
     __shared__ int s_next;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int chunk = (int)(lb / (unsigned)nranges), range = (int)(lb % (unsigned)nranges);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    const int pi = chunk * CW + lane;
-    const bool pvalid = lane < CW && pi < Kp;
+    // the lane's direction pair in the chunk, and with SM the half of the wave (x bit of its
+    // target octants)
+    const int cl = SM ? lane % CW : (lane < CW ? lane : CW - 1);
+    const int hb = SM ? lane / CW : 0;
+    const int pi = chunk * CW + cl;
+    const bool pvalid = (SM || lane < CW) && pi < Kp;
     // idle lanes work on the first pair and store nothing
     const int k1 = pairs[2 * (pvalid ? pi : 0)], k2 = pairs[2 * (pvalid ? pi : 0) + 1];
-    const int cl = lane < CW ? lane : CW - 1;
     // T_{g rep}(s_k1) = T_rep(s_{tperm[g][k1]}) of every transfer vector, row t of the table
     const int32_t* row_tix = rows + 27 * 27;
     const int32_t* farm = rows + 27 * 27 + kNumOffsets;
@@ -563,9 +570,11 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
         for (int o = 0; o < 8; ++o) tm |= (__ballot(ot_l == o) != 0 ? 1 : 0) << o;
         for (int r = 0; r < nrhs; ++r) {
             const C* Mr = M + (int64_t)r * plane;
-            C acc[8][2];
+            // per target octant (with SM: per octant 2 j + hb of this half, at j)
+            constexpr int NO = SM ? 4 : 8;
+            C acc[NO][2];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) acc[o][0] = acc[o][1] = cz<C>();
+            for (int o = 0; o < NO; ++o) acc[o][0] = acc[o][1] = cz<C>();
             uint64_t occ = occ0;
             while (occ) {
                 const int D = __builtin_ctzll(occ);
@@ -588,18 +597,21 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
                         const C* mp = Mr + (int64_t)ci * K;
                         const C m1 = mp[k1], m2 = mp[k2];
 #pragma unroll
-                        for (int ot = 0; ot < 8; ++ot) {
-                            if (!((m >> ot) & 1)) continue;
+                        for (int j = 0; j < 4; ++j) {
+                            // the target octants 2 j (half 0) and 2 j + 1 (half 1)
+                            const int mj = (m >> (2 * j)) & 3;
+                            if (!mj) continue;
                             __asm__ __volatile__("");
-                            const int e = ((os & 1) - (ot & 1) + 1) + 3 * (((os >> 1) & 1) - ((ot >> 1) & 1) + 1) +
-                                          9 * (((os >> 2) & 1) - ((ot >> 2) & 1) + 1);
-                            const int row = rr[e];
-                            cmac(acc[ot][0], m1, Ts[row][cl]);
-                            cmac(acc[ot][1], m2, Ts[kNumOffsets - 1 - row][cl]);
+                            const int e = ((os & 1) + 1) + 3 * (((os >> 1) & 1) - (j & 1) + 1) +
+                                          9 * (((os >> 2) & 1) - ((j >> 1) & 1) + 1);
+                            const int row = hb ? rr[e - 1] : rr[e];
+                            if ((mj >> hb) & 1) {
+                                cmac(acc[j][0], m1, Ts[row][cl]);
+                                cmac(acc[j][1], m2, Ts[kNumOffsets - 1 - row][cl]);
+                            }
                         }
                     }
-                    continue;
-                }
+                } else {
                 // source signatures of the present octants at s and -s
                 C ms[8][2];
 #pragma unroll
@@ -629,15 +641,18 @@ __global__ __launch_bounds__(kWave * kTW) void m2lt_kernel(
                         cmac(acc[ot][1], ms[os][1], Ts[kNumOffsets - 1 - row][cl]);
                     }
                 }
+                }
             }
             if (pvalid)
                 for (int i = 0; i < tn; ++i) {
                     const int c = tb + i;
                     const int o = __builtin_amdgcn_readfirstlane(octant[c]);
+                    if (SM && (o & 1) != hb) continue;   // the other half holds this child
+                    const int oa = SM ? o >> 1 : o;
                     C* op = out + (int64_t)r * plane + (int64_t)c * K;
 #pragma unroll
-                    for (int oo = 0; oo < 8; ++oo)
-                        if (oo == o) {
+                    for (int oo = 0; oo < NO; ++oo)
+                        if (oo == oa) {
                             op[k1] = acc[oo][0];
                             op[k2] = acc[oo][1];
                         }
