@@ -277,7 +277,8 @@ typedef struct {
                                    largest that does not exceed nrhs */
     int32_t rs_slab[4];         /* resample k-slab depth (16, 32 or 64; FP64 plans take 32 for 64)
                                    of step 1, steps 2+3, upward steps 4+5 and downward steps 4+5;
-                                   default 16, 32, 32, 16 */
+                                   the quarter-range forms of steps 1 and 5 take 16 or 32 (32 for
+                                   64; FP64: 16); default 16, 32, 32, 16 */
     int32_t m2l_by_parent;      /* M2L form. 2 (default): by parent pairs, with the transfer
                                    functions of a chunk of m2l_chunk directions gathered into LDS
                                    once per block and reused for a range of parents (FP64 plans:
