@@ -482,13 +482,14 @@ int common_nphi(const LevelData& S, const LevelData& D)
 void quarter_block(int N, int M, int ld, double* blk)
 {
     const int h = N / 2, q = N / 4, Q = M / 4;
-    auto de = [&](int m, int j) { return 0.5 * (dirichlet(N, M, m, j) + dirichlet(N, M, m + h, j)); };
-    auto dodd = [&](int m, int j) { return 0.5 * (dirichlet(N, M, m, j) - dirichlet(N, M, m + h, j)); };
     for (int m = 0; m <= q; ++m) {
         const int r = (h - m) % h;
         const double wt = (m == 0 || m == q) ? 0.5 : 1.0;
         for (int j = 0; j <= Q; ++j) {
-            const double e0 = de(m, j), e1 = de(r, j), o0 = dodd(m, j), o1 = m == 0 ? -dodd(0, j) : dodd(r, j);
+            const double a = dirichlet(N, M, m, j), b = dirichlet(N, M, m + h, j);
+            const double c = m == 0 ? a : dirichlet(N, M, r, j), d = m == 0 ? b : dirichlet(N, M, r + h, j);
+            const double e0 = 0.5 * (a + b), e1 = 0.5 * (c + d), o0 = 0.5 * (a - b);
+            const double o1 = m == 0 ? -o0 : 0.5 * (c - d);
             blk[((size_t)m * 4 + 0) * ld + j] = wt * 0.5 * (e0 + e1);
             blk[((size_t)m * 4 + 1) * ld + j] = wt * 0.5 * (e0 - e1);
             blk[((size_t)m * 4 + 2) * ld + j] = wt * 0.5 * (o0 - o1);
@@ -523,10 +524,16 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
         if (v % 2 != 0) fail(FFMM_ERR_INTERNAL, "odd quadrature row length");
     for (int v : D.par.nphi)
         if (v % 2 != 0) fail(FFMM_ERR_INTERNAL, "odd quadrature row length");
+    // quarter-range row steps where the common phi length makes the contractions long (then the
+    // half-range operators of this transition are not built)
+    bool mult4 = na % 4 == 0;
+    for (int v : S.par.nphi) mult4 = mult4 && v % 4 == 0;
+    for (int v : D.par.nphi) mult4 = mult4 && v % 4 == 0;
+    rs.quarter = mult4 && na >= (p->opt.quarter_nphi > 0 ? p->opt.quarter_nphi : kQuarterMinNphi);
     const int H = na / 2;
     rs.ldj = (H + 3) / 4 * 4;
-    std::vector<double> d1h((size_t)S.K * rs.ldj, 0.0);
-    for (int n = 0; n < S.nrows; ++n) {
+    std::vector<double> d1h(rs.quarter ? 0 : (size_t)S.K * rs.ldj, 0.0);
+    for (int n = 0; n < S.nrows && !rs.quarter; ++n) {
         const int len = S.par.nphi[n], h = len / 2;
         double* blk = &d1h[(size_t)S.row_off[n] * rs.ldj];   // (row_off / 2) source pairs x 2 x ldj
         for (int m = 0; m < h; ++m)
@@ -537,7 +544,7 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
             }
     }
     std::vector<int> off5(D.nrows + 1, 0);
-    {
+    if (!rs.quarter) {
         int64_t o = 0;
         for (int n = 0; n < D.nrows; ++n) {
             o += (int64_t)H * 2 * ((D.par.nphi[n] / 2 + 3) / 4 * 4);
@@ -546,7 +553,7 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
         }
     }
     std::vector<double> d5h((size_t)off5[D.nrows], 0.0);
-    for (int n = 0; n < D.nrows; ++n) {
+    for (int n = 0; n < D.nrows && !rs.quarter; ++n) {
         const int len = D.par.nphi[n], h = len / 2, ld = (h + 3) / 4 * 4;
         double* blk = &d5h[(size_t)off5[n]];
         for (int j = 0; j < H; ++j)
@@ -559,12 +566,7 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
     for (int t = 0; t < rs.nt_src; ++t)
         for (int tp = 0; tp < rs.nt_dst; ++tp)
             dth[(size_t)t * ldt + tp] = dirichlet(rs.nt_src, rs.nt_dst, t, tp);
-    upload_real<R>(p->arena, &rs.d1h, d1h, s);
-    // quarter-range row steps where the common phi length makes the contractions long
-    bool mult4 = na % 4 == 0;
-    for (int v : S.par.nphi) mult4 = mult4 && v % 4 == 0;
-    for (int v : D.par.nphi) mult4 = mult4 && v % 4 == 0;
-    rs.quarter = mult4 && na >= (p->opt.quarter_nphi > 0 ? p->opt.quarter_nphi : kQuarterMinNphi);
+    if (!rs.quarter) upload_real<R>(p->arena, &rs.d1h, d1h, s);
     if (rs.quarter) {
         const int Q = na / 4;
         rs.ldq = (Q + 1 + 3) / 4 * 4;
@@ -607,9 +609,11 @@ void make_resampler(ffmm_plan* p, const LevelData& S, const LevelData& D, Resamp
             }
         upload_real<R>(p->arena, &rs.dth_h, dh, s);
     }
-    upload_real<R>(p->arena, &rs.d5h, d5h, s);
-    off5.pop_back();
-    rs.d5h_off = upload_int(p->arena, off5, s);
+    if (!rs.quarter) {
+        upload_real<R>(p->arena, &rs.d5h, d5h, s);
+        off5.pop_back();
+        rs.d5h_off = upload_int(p->arena, off5, s);
+    }
     rs.d_src_row_off = S.d_row_off;
     rs.d_src_nphi = S.d_nphi;
     rs.d_dst_row_off = D.d_row_off;
