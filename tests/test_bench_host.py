@@ -61,3 +61,45 @@ def test_stage_roofline_takes_the_largest_bound():
     # M2L: 8 flops per interaction-list entry and direction over every level
     assert bench.stage_work(info, "m2l")["flops"] == 8.0 * (200 * 400 + 5000 * 100)
     assert bench.stage_work(info, "leaf_m2l")["flops"] == 8.0 * 5000 * 100
+
+
+def _counter_csv(path, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name",
+                                          "Counter_Value"])
+        w.writeheader()
+        for d, name, counter, value in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Grid_Size": 256, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_traffic_total_sums_a_kernel_group_per_call(tmp_path):
+    """traffic-total: the scaled FETCH_SIZE + WRITE_SIZE of every dispatch of the group (name
+    prefixes, instances of one dispatch summed), over the number of calls of the reference kernel;
+    other kernels are left out."""
+    from argparse import Namespace
+    from paper_0911_4114_amd.profiling import traffic_total
+    k1 = "void ffmm::(anonymous namespace)::rs1_mfma<float, false, 16>(long)"
+    k2 = "void ffmm::(anonymous namespace)::rs5q_mfma<float, true, 32>(long)"
+    other = "void ffmm::(anonymous namespace)::l2p_kernel<float>(int)"
+    ref = "void ffmm::(anonymous namespace)::p2p_kernel<float, HIP_vector_type<float, 2u>, false, false, 1>(double)"
+    copy = "__amd_rocclr_copyBuffer"
+    fetch = [(1, ref, "FETCH_SIZE", 1.0), (2, k1, "FETCH_SIZE", 10.0), (2, k1, "FETCH_SIZE", 6.0),
+             (3, k2, "FETCH_SIZE", 20.0), (4, other, "FETCH_SIZE", 1000.0), (5, ref, "FETCH_SIZE", 1.0),
+             (6, k1, "FETCH_SIZE", 8.0)]
+    write = [(1, ref, "WRITE_SIZE", 1.0), (2, k1, "WRITE_SIZE", 4.0), (3, k2, "WRITE_SIZE", 2.0),
+             (4, other, "WRITE_SIZE", 500.0), (5, ref, "WRITE_SIZE", 1.0), (6, k1, "WRITE_SIZE", 2.0)]
+    _counter_csv(tmp_path / "f.csv", fetch)
+    _counter_csv(tmp_path / "w.csv", write)
+    # copy probe: 2048 bytes moved, FETCH reads half (1 KiB), WRITE all (2 KiB): scales 2 and 1
+    _counter_csv(tmp_path / "cf.csv", [(1, copy, "FETCH_SIZE", 1.0)])
+    _counter_csv(tmp_path / "cw.csv", [(1, copy, "WRITE_SIZE", 2.0)])
+    a = Namespace(prefix=["rs1_mfma", "rs5q_mfma"], per="p2p_kernel<float, float2, false, false, 1>",
+                  fetch=str(tmp_path / "f.csv"), write=str(tmp_path / "w.csv"),
+                  copy_fetch=str(tmp_path / "cf.csv"), copy_write=str(tmp_path / "cw.csv"), copy_bytes=2048,
+                  copy_kernel=copy)
+    out = dict(line.split(": ") for line in traffic_total(a).splitlines())
+    assert int(out["calls"]) == 2
+    # fetch (10 + 6 + 20 + 8) KiB x 2 + write (4 + 2 + 2) KiB x 1, over 2 calls
+    assert float(out["hbm_bytes_per_call"]) == pytest.approx(1024.0 * (2 * 44 + 8) / 2)
